@@ -1,0 +1,163 @@
+/*
+ * aoresp.h -- C ABI of libaoresp: outlier-robust rotation estimation by
+ * stereographic projection and spatial voting, on AMD Instinct MI355X (gfx950).
+ *
+ * Paper: T. Xu, Y. Liu, X. Wang, Z.-X. Yang, "Accelerating Outlier-robust
+ * Rotation Estimation by Stereographic Projection" (arXiv 2502.06337).
+ *
+ * Problem (Sec. I, Eq. (1)): given point sets P = {p_i} and Q = {q_i} with
+ * correspondence by index, find a rotation R (or several) and the inlier set
+ * C = {i : q_i = R p_i + noise}.  Method (Algorithm 1, Sec. III-IV):
+ *   1. every pair restricts the axis to the great circle r . (p_i - q_i) = 0
+ *      (Eq. (4)); stereographic projection (Eq. (7)) maps it to a circle or
+ *      line in the unit disk (Sec. IV, projected-circle equation);
+ *   2. the circles vote into a G x G accumulator over [-1, 1]^2: a cell gets
+ *      one vote per circle through it (Fig. 3(c));
+ *   3. the peak cell (optionally refined on an M x M grid over the 3 x 3
+ *      cells around it), back-projected by Eq. (8), is the axis;
+ *   4. every pair votes its signed rotation angle about that axis into a
+ *      B-bin histogram over [-pi, pi) (Sec. IV-B, Eq. (10));
+ *   5. R = Rodrigues(axis, angle) (Eq. (2)); inliers: ||R p_i - q_i|| <= tau.
+ * Several rotations (Sec. IV-D): the top-k peaks of the same accumulator with
+ * non-maximum suppression, each with its own histogram and R.
+ *
+ * Conventions for every entry point:
+ *   - P and Q are structure-of-arrays float32 of shape (3, n): x[0..n),
+ *     y[0..n), z[0..n).  Host variants take host pointers; *_dev variants take
+ *     device pointers on the current HIP device and a hipStream_t (as void*,
+ *     NULL = default stream) and return after the work is enqueued and the
+ *     small result struct has been copied back (they synchronise the stream).
+ *   - The library never keeps or frees caller memory.  It caches a workspace
+ *     per device (grown on demand) and serialises calls that share it.
+ *   - Results depend only on (P, Q, n, params): binary32 arithmetic with no
+ *     contraction, integer votes, ties broken towards the lowest index.
+ *   - Outputs are written only when the status is AORESP_OK or AORESP_ENODATA.
+ *   - A correspondence with p_i - q_i = 0 or a non-finite coordinate casts no
+ *     axis vote; one whose angle inputs are (0, 0) or non-finite casts no
+ *     angle vote; its mask entry is 0 unless its residual passes the test.
+ */
+#ifndef AORESP_H
+#define AORESP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AORESP_OK = 0,
+    AORESP_EINVAL = -1,    /* null pointer, parameter out of range */
+    AORESP_ENOMEM = -2,    /* device memory or budget exhausted */
+    AORESP_EDEVICE = -3,   /* HIP error, or an internal consistency check failed */
+    AORESP_ENODATA = -4,   /* n < 2 or no vote: R = I, counts 0 */
+    AORESP_EBUSY = -5,     /* request not finished yet (poll) */
+    AORESP_ETIMEDOUT = -6  /* request exceeded its deadline */
+} aoresp_status;
+
+/* Solve parameters.  Zero-initialised fields take the documented defaults. */
+typedef struct {
+    uint32_t grid;           /* G: power of two in [64, 4096]; 0 = aoresp_grid_for_n(n) */
+    uint32_t refine_grid;    /* M: 0 = no refinement, else power of two in [8, 128], G*M <= 262144 */
+    uint32_t refine_halfwin; /* w: refinement window (2w+1)^2 coarse cells, clipped; 0 -> 1 */
+    uint32_t angle_bins;     /* B: bins over [-pi, pi); 0 -> 360; at most 8192 */
+    uint32_t nms_radius;     /* top-k suppression radius in coarse cells; 0 -> 5 */
+    float inlier_thresh;     /* tau on ||R p - q||; <= 0 -> 0.05 */
+} aoresp_params;
+
+/* Result of one rotation. */
+typedef struct {
+    float R[9];              /* row-major, maps p to q */
+    float axis[3];           /* unit axis on the southern hemisphere (Eq. (8)) */
+    float angle;             /* signed angle in [-pi, pi): histogram bin centre */
+    uint32_t grid;           /* G used */
+    uint32_t peak_cell;      /* iy*G + ix of the coarse peak */
+    uint32_t fine_cell;      /* jy*M + jx of the refined peak (0 without refinement) */
+    uint32_t angle_bin;      /* histogram bin of the angle */
+    uint32_t axis_votes;     /* votes of the coarse peak */
+    uint32_t fine_votes;     /* votes of the refined peak */
+    uint32_t angle_votes;    /* votes of the angle bin */
+    uint32_t n_inliers;      /* number of i with ||R p_i - q_i|| <= tau */
+} aoresp_result;
+
+/* Grid resolution chosen for n when params.grid == 0: a pure function of n
+ * (so batched, served and one-at-a-time solves agree). */
+uint32_t aoresp_grid_for_n(uint64_t n);
+
+/* Single rotation (Sec. I; Algorithm 1).  P, Q: host (3, n) float32.
+ * inlier_mask: n bytes or NULL.  ENODATA if n < 2 or the accumulator is empty. */
+aoresp_status est_rotation(const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                           aoresp_result* out, uint8_t* inlier_mask);
+aoresp_status est_rotation_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                               aoresp_result* out, uint8_t* inlier_mask, void* hip_stream);
+
+/* Several rotations (Sec. IV-D): greedy top-k peaks with suppression of a
+ * disk of nms_radius cells around each earlier peak and of the disk of radius
+ * nms_radius*h around the projection of its antipodal axis.  out: k entries;
+ * masks: k*n bytes (row t = peak t) or NULL; *k_found = peaks found (<= k).
+ * k in [1, 8]. */
+aoresp_status est_rotations_topk(const float* P, const float* Q, size_t n, uint32_t k,
+                                 const aoresp_params* prm, aoresp_result* out, uint8_t* masks,
+                                 uint32_t* k_found);
+aoresp_status est_rotations_topk_dev(const float* P, const float* Q, size_t n, uint32_t k,
+                                     const aoresp_params* prm, aoresp_result* out, uint8_t* masks,
+                                     uint32_t* k_found, void* hip_stream);
+
+/* Many independent instances in one launch per stage.  Instance b owns
+ * columns [off[b], off[b+1]) of the (3, off[batch]) SoA arrays P and Q.
+ * prm: 1 shared entry or `batch` entries (prm_count).  out: batch entries;
+ * masks: off[batch] bytes or NULL.  Instance b's result equals est_rotation
+ * on its own columns with the same parameters (grid included). */
+aoresp_status est_rotation_batch(const float* P, const float* Q, const uint64_t* off, uint32_t batch,
+                                 const aoresp_params* prm, uint32_t prm_count, aoresp_result* out,
+                                 uint8_t* masks);
+aoresp_status est_rotation_batch_dev(const float* P, const float* Q, const uint64_t* off, uint32_t batch,
+                                     const aoresp_params* prm, uint32_t prm_count, aoresp_result* out,
+                                     uint8_t* masks, void* hip_stream);
+
+/* Steps of the path, exposed for verification.  All device pointers.
+ * Coarse accumulator: grid = G*G uint32 (iy*G + ix).                        */
+aoresp_status aoresp_coarse_grid_dev(const float* P, const float* Q, size_t n, uint32_t G, uint32_t* grid,
+                                     void* hip_stream);
+/* Full single solve that also copies the coarse grid (G*G), the fine grid
+ * (M*M, if refining) and the angle histogram (B) to the given device buffers
+ * (each may be NULL). */
+aoresp_status aoresp_solve_debug_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                                     aoresp_result* out, uint8_t* inlier_mask, uint32_t* grid_out,
+                                     uint32_t* fine_out, uint32_t* hist_out, void* hip_stream);
+
+/* Request loop: continuous batching of solves under a device-memory budget.
+ * aoresp_submit copies the inputs and returns at once; requests that arrive
+ * while others run are admitted as memory and slots free up and run in the
+ * next batched step.  Results equal est_rotation on the same inputs.        */
+typedef struct aoresp_server aoresp_server;
+typedef struct {
+    size_t hbm_budget_bytes;  /* device bytes for admitted requests; 0 -> 8 GiB */
+    uint32_t max_slots;       /* requests in one batched step; 0 -> 256 */
+    uint32_t timeout_us;      /* per-request deadline from submit; 0 = none */
+} aoresp_server_cfg;
+
+aoresp_status aoresp_server_create(const aoresp_server_cfg* cfg, aoresp_server** out);
+/* P, Q: host (3, n) float32, copied.  ENOMEM if the request alone exceeds the
+ * budget.  *req_id identifies the request for aoresp_poll. */
+aoresp_status aoresp_submit(aoresp_server* s, const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                            uint64_t* req_id);
+/* timeout_us: 0 = do not wait, < 0 = wait until done.  EBUSY if not done.
+ * On completion the request is released; mask (n bytes) may be NULL. */
+aoresp_status aoresp_poll(aoresp_server* s, uint64_t req_id, aoresp_result* out, uint8_t* mask,
+                          int64_t timeout_us);
+/* Latency percentiles (submit to completion) over completed requests. */
+aoresp_status aoresp_server_stats(aoresp_server* s, double* p50_us, double* p99_us, double* req_per_s,
+                                  uint64_t* completed);
+/* Drains queued and running requests, then frees everything. */
+void aoresp_server_destroy(aoresp_server* s);
+
+const char* aoresp_strerror(aoresp_status st);
+/* Library build identification (string constant). */
+const char* aoresp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AORESP_H */
