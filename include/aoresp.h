@@ -127,6 +127,14 @@ aoresp_status aoresp_solve_debug_dev(const float* P, const float* Q, size_t n, c
                                      aoresp_result* out, uint8_t* inlier_mask, uint32_t* grid_out,
                                      uint32_t* fine_out, uint32_t* hist_out, void* hip_stream);
 
+/* One single solve with HIP events recorded on hip_stream between its stages;
+ * ms_out receives *n_stages durations in milliseconds, in this order: setup
+ * (per-correspondence records, zeroing), coarse vote, peak search,
+ * refinement (fine vote, fine peak, axis), angle histogram and rotation,
+ * inlier mask.  For measurement; results are discarded. */
+aoresp_status aoresp_stage_times_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                                     float* ms_out, uint32_t* n_stages, void* hip_stream);
+
 /* Request loop: continuous batching of solves under a device-memory budget.
  * aoresp_submit copies the inputs and returns at once; requests that arrive
  * while others run are admitted as memory and slots free up and run in the

@@ -71,6 +71,8 @@ SIGNATURES = {
     "aoresp_coarse_grid_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.c_uint32, _u32p, _vp]),
     "aoresp_solve_debug_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(Result), _u8p,
                                          _u32p, _u32p, _u32p, _vp]),
+    "aoresp_stage_times_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(C.c_float),
+                                         C.POINTER(C.c_uint32), _vp]),
     "aoresp_server_create": (C.c_int, [C.POINTER(ServerCfg), C.POINTER(C.c_void_p)]),
     "aoresp_submit": (C.c_int, [_vp, _fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(C.c_uint64)]),
     "aoresp_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(Result), _u8p, C.c_int64]),

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -11,9 +13,25 @@
 
 namespace aoresp {
 
-#define AOR_HIP(expr)                                  \
-    do {                                               \
-        if ((expr) != hipSuccess) return AORESP_EDEVICE; \
+// Set AORESP_DEBUG=1 to print the HIP error behind an AORESP_EDEVICE.
+static bool debug_on() {
+    static int on = -1;
+    if (on < 0) {
+        const char* e = getenv("AORESP_DEBUG");
+        on = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
+static aoresp_status hip_fail(hipError_t e, const char* what, int line) {
+    if (debug_on()) fprintf(stderr, "aoresp: %s failed at api.cpp:%d: %s\n", what, line, hipGetErrorString(e));
+    return AORESP_EDEVICE;
+}
+
+#define AOR_HIP(expr)                                        \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr, __LINE__); \
     } while (0)
 
 static bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
@@ -159,8 +177,11 @@ int coarse_chunks(DeviceCtx* ctx, int64_t n, int G) {
 
 aoresp_status enqueue_solve(DeviceCtx* ctx, const float* P, const float* Q, int64_t n, const ResolvedParams& rp,
                             int npk, uint8_t* masks, uint32_t* grid_out, uint32_t* fine_out, uint32_t* hist_out,
-                            hipStream_t s) {
+                            hipStream_t s, hipEvent_t* marks) {
     SolveBuffers& b = ctx->buf;
+    auto mark = [&](int k) {
+        if (marks) (void)hipEventRecord(marks[k], s);
+    };
     const int G = rp.G, M = rp.M, B = rp.B;
     aoresp_status st;
     if ((st = b.abc.ensure((size_t)n * sizeof(float4))) != AORESP_OK) return st;
@@ -184,22 +205,27 @@ aoresp_status enqueue_solve(DeviceCtx* ctx, const float* P, const float* Q, int6
     uint32_t* hist = b.hist.as<uint32_t>();
     unsigned long long* keys = b.keys.as<unsigned long long>();
 
+    mark(0);
     launch_zero_u32(b.err.as<uint32_t>(), 1, s);
     launch_zero_u32(reinterpret_cast<uint32_t*>(keys), 2 * kMaxPeaks, s);
     launch_zero_u32(reinterpret_cast<uint32_t*>(stt), kMaxPeaks * sizeof(PeakState) / 4, s);
     launch_zero_u32(reinterpret_cast<uint32_t*>(res), kMaxPeaks * sizeof(aoresp_result) / 4, s);
     launch_arc_setup(P, Q, n, G, R, s);
     launch_zero_u32(b.grid.as<uint32_t>(), (size_t)G * G, s);
+    mark(1);
     launch_coarse_vote(R, n, G, disk, b.grid.as<uint32_t>(), b.err.as<uint32_t>(), coarse_chunks(ctx, n, G), s);
+    mark(2);
     for (int t = 0; t < npk; ++t) {
         launch_peak(b.grid.as<uint32_t>(), G, (int64_t)G * G, stt, t, rp.rad, keys + t, s);
         launch_peak_finish(keys + t, G, M, rp.w, stt, t, s);
     }
+    mark(3);
     if (M > 0) launch_zero_u32(fine, (size_t)npk * M * M, s);
     for (int t = 0; t < npk; ++t) {
         if (M > 0) launch_fine_vote(R, n, M, stt, t, fine + (size_t)t * M * M, b.err.as<uint32_t>(), s);
         launch_fine_peak(fine + (size_t)t * (M > 0 ? M * M : 0), G, M, stt, t, s);
     }
+    mark(4);
     launch_zero_u32(hist, (size_t)npk * B, s);
     // histograms of several peaks share one pass while the LDS allows it
     int per = (int)((160 * 1024 - (size_t)B * 8) / ((size_t)B * 4));
@@ -209,13 +235,15 @@ aoresp_status enqueue_solve(DeviceCtx* ctx, const float* P, const float* Q, int6
         launch_angle_hist(P, Q, n, stt + t0, cnt, B, at->tc, at->ts, hist + (size_t)t0 * B, s);
     }
     for (int t = 0; t < npk; ++t) launch_angle_peak(hist, B, at->th, at->ct, at->st, stt, t, G, res, s);
+    mark(5);
     launch_inliers(P, Q, n, stt, npk, rp.tau, res, masks, s);
+    mark(6);
     if (grid_out)
         AOR_HIP(hipMemcpyAsync(grid_out, b.grid.ptr, (size_t)G * G * 4, hipMemcpyDeviceToDevice, s));
     if (fine_out && M > 0)
         AOR_HIP(hipMemcpyAsync(fine_out, fine, (size_t)npk * M * M * 4, hipMemcpyDeviceToDevice, s));
     if (hist_out) AOR_HIP(hipMemcpyAsync(hist_out, hist, (size_t)npk * B * 4, hipMemcpyDeviceToDevice, s));
-    if (hipGetLastError() != hipSuccess) return AORESP_EDEVICE;
+    AOR_HIP(hipGetLastError());
     return AORESP_OK;
 }
 
@@ -225,7 +253,10 @@ aoresp_status finish_solve(DeviceCtx* ctx, int npk, aoresp_result* out, uint32_t
     AOR_HIP(hipMemcpyAsync(b.h_st, b.st.ptr, sizeof(PeakState) * npk, hipMemcpyDeviceToHost, s));
     AOR_HIP(hipMemcpyAsync(b.h_err, b.err.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     AOR_HIP(hipStreamSynchronize(s));
-    if (*b.h_err) return AORESP_EDEVICE;
+    if (*b.h_err) {
+        if (debug_on()) fprintf(stderr, "aoresp: internal check flag 0x%x\n", *b.h_err);
+        return AORESP_EDEVICE;
+    }
     uint32_t found = 0;
     for (int t = 0; t < npk; ++t) {
         out[t] = b.h_res[t];
@@ -374,7 +405,35 @@ aoresp_status aoresp_coarse_grid_dev(const float* P, const float* Q, size_t n, u
     AOR_HIP(hipGetLastError());
     AOR_HIP(hipMemcpyAsync(b.h_err, b.err.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     AOR_HIP(hipStreamSynchronize(s));
+    if (*b.h_err && debug_on()) fprintf(stderr, "aoresp: internal check flag 0x%x\n", *b.h_err);
     return *b.h_err ? AORESP_EDEVICE : AORESP_OK;
+}
+
+aoresp_status aoresp_stage_times_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                                     float* ms_out, uint32_t* n_stages, void* hip_stream) {
+    if (!ms_out || !n_stages || n < 2 || !P || !Q || n > (size_t)INT32_MAX) return AORESP_EINVAL;
+    ResolvedParams rp;
+    aoresp_status st = resolve_params(prm, n, rp);
+    if (st != AORESP_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;
+    DeviceCtx* ctx = device_ctx();
+    if (!ctx) return AORESP_EDEVICE;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    hipEvent_t ev[kNumStages + 1];
+    for (int k = 0; k <= kNumStages; ++k) AOR_HIP(hipEventCreate(&ev[k]));
+    st = enqueue_solve(ctx, P, Q, (int64_t)n, rp, 1, nullptr, nullptr, nullptr, nullptr, s, ev);
+    aoresp_result tmp;
+    if (st == AORESP_OK) st = finish_solve(ctx, 1, &tmp, nullptr, s);
+    if (st == AORESP_OK || st == AORESP_ENODATA) {
+        for (int k = 0; k < kNumStages; ++k) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[k], ev[k + 1]) != hipSuccess) ms = -1.0f;
+            ms_out[k] = ms;
+        }
+        *n_stages = kNumStages;
+    }
+    for (int k = 0; k <= kNumStages; ++k) (void)hipEventDestroy(ev[k]);
+    return st;
 }
 
 const char* aoresp_strerror(aoresp_status st) {

@@ -38,11 +38,15 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#ifndef AOR_HD
+#define AOR_HD __host__ __device__
+#endif
+
 namespace aoresp {
 
 // sigma * F-hat at (x, y): a, b, c already multiplied by sigma (exact negation).
 // xx = x*x and ax = a_loc*x are per-line terms.
-__device__ __forceinline__ float vertex_F(float b_loc, float c, float xx, float ax, float y) {
+AOR_HD __forceinline__ float vertex_F(float b_loc, float c, float xx, float ax, float y) {
     float yy = y * y;
     float w = (xx + yy) - 1.0f;
     float cw = c * w;
@@ -55,7 +59,7 @@ __device__ __forceinline__ float vertex_F(float b_loc, float c, float xx, float 
 // Roots y of c y^2 + 2 b y + K = 0 with K = c (x^2 - 1) + 2 a x, i.e. where
 // the curve crosses the vertex line at along-coordinate x (float64; c >= 0).
 // sel = 0 returns the lower root, 1 the upper one; a line (c == 0) has one.
-__device__ __forceinline__ double cross_root(double a, double b, double c, double x, int sel) {
+AOR_HD __forceinline__ double cross_root(double a, double b, double c, double x, int sel) {
     double K = c * (x * x - 1.0) + 2.0 * a * x;
     if (c == 0.0) return -K / (2.0 * b);
     double t = c * x + a;
@@ -70,10 +74,10 @@ __device__ __forceinline__ double cross_root(double a, double b, double c, doubl
     return sel ? hi : lo;
 }
 
-__device__ __forceinline__ int32_t pack_range(int s, int e) {
+AOR_HD __forceinline__ int32_t pack_range(int s, int e) {
     return (int32_t)((uint32_t)(uint16_t)(int16_t)s | ((uint32_t)(uint16_t)(int16_t)e << 16));
 }
-__device__ __forceinline__ void unpack_range(int32_t v, int& s, int& e) {
+AOR_HD __forceinline__ void unpack_range(int32_t v, int& s, int& e) {
     s = (int)(int16_t)(uint16_t)((uint32_t)v & 0xFFFFu);
     e = (int)(int16_t)(uint16_t)((uint32_t)v >> 16);
 }

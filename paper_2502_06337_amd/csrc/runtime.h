@@ -70,9 +70,11 @@ int coarse_chunks(DeviceCtx* ctx, int64_t n, int G);
 // Enqueue a full solve of `npk` peaks on stream s into ctx->buf (caller holds
 // ctx->mu).  P, Q, masks are device pointers.  grid/fine/hist debug copies may
 // be null.  Does not synchronise.
+// Stage boundaries recorded when `marks` is non-null (kNumStages + 1 events).
+enum Stage { kStageSetup = 0, kStageCoarse, kStagePeak, kStageFine, kStageAngle, kStageInliers, kNumStages };
 aoresp_status enqueue_solve(DeviceCtx* ctx, const float* P, const float* Q, int64_t n, const ResolvedParams& rp,
                             int npk, uint8_t* masks, uint32_t* grid_out, uint32_t* fine_out, uint32_t* hist_out,
-                            hipStream_t s);
+                            hipStream_t s, hipEvent_t* marks = nullptr);
 // Copy results back, synchronise, translate into statuses.
 aoresp_status finish_solve(DeviceCtx* ctx, int npk, aoresp_result* out, uint32_t* k_found, hipStream_t s);
 
