@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <memory>
 #include <vector>
 
@@ -89,12 +90,7 @@ DeviceCtx* device_ctx() {
     ctx->device = dev;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
-    if (hipStreamCreateWithFlags(&ctx->buf.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipHostMalloc((void**)&ctx->buf.h_res, sizeof(aoresp_result) * kMaxPeaks, hipHostMallocDefault) !=
-            hipSuccess ||
-        hipHostMalloc((void**)&ctx->buf.h_st, sizeof(PeakState) * kMaxPeaks, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&ctx->buf.h_err, sizeof(uint32_t), hipHostMallocDefault) != hipSuccess)
-        return nullptr;
+    if (hipStreamCreateWithFlags(&ctx->ws.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
     DeviceCtx* raw = ctx.get();
     g_ctx[dev] = std::move(ctx);
     return raw;
@@ -162,108 +158,246 @@ const int16_t* disk_table(DeviceCtx* ctx, int G) {
     return d;
 }
 
-// Work split of the coarse vote: enough (band, chunk) work-groups to cover the
-// chip twice, without chunks smaller than a few thousand correspondences.
-int coarse_chunks(DeviceCtx* ctx, int64_t n, int G) {
-    int bw = coarse_band_width(G);
-    int nbands = (G + bw - 1) / bw;
-    int target = 2 * ctx->cu_count;
-    int ch = (target + 2 * nbands - 1) / (2 * nbands);
-    int64_t maxch = (n + 4095) / 4096;
-    if (ch > maxch) ch = (int)maxch;
-    if (ch < 1) ch = 1;
-    return ch;
+aoresp_status HostBuf::ensure(size_t need) {
+    if (need <= bytes) return AORESP_OK;
+    if (ptr) (void)hipHostFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    size_t want = need + need / 4 + 4096;
+    if (hipHostMalloc(&ptr, want, hipHostMallocDefault) != hipSuccess) {
+        ptr = nullptr;
+        (void)hipGetLastError();
+        return AORESP_ENOMEM;
+    }
+    bytes = want;
+    return AORESP_OK;
 }
 
-aoresp_status enqueue_solve(DeviceCtx* ctx, const float* P, const float* Q, int64_t n, const ResolvedParams& rp,
-                            int npk, uint8_t* masks, uint32_t* grid_out, uint32_t* fine_out, uint32_t* hist_out,
-                            hipStream_t s, hipEvent_t* marks) {
-    SolveBuffers& b = ctx->buf;
+// Batch layout.  Coarse vote items: (instance, pass, band, chunk of arcs),
+// sized so that one item carries about kVoteTarget votes, ordered largest
+// first for the persistent work-groups.  Peak items: 64K cells.  Correspondence
+// items (refinement, angle histogram): 4096 correspondences.
+static constexpr double kVoteTarget = 3.0e6;
+static constexpr int kCellChunk = 65536;
+static constexpr int kCorrChunk = 4096;
+
+aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps, const int* npk,
+                         Plan& plan) {
+    plan = Plan();
+    plan.insts.resize(ninst);
+    std::vector<std::pair<double, int4>> votes;
+    size_t hist_lds = 0;
+    for (int b = 0; b < ninst; ++b) {
+        const ResolvedParams& rp = rps[b];
+        Inst& I = plan.insts[b];
+        std::memset(&I, 0, sizeof(I));
+        I.off = off[b];
+        int64_t n = off[b + 1] - off[b];
+        if (n < 0 || n > INT32_MAX) return AORESP_EINVAL;
+        I.n = (int32_t)n;
+        I.G = rp.G;
+        I.M = rp.M;
+        I.w = rp.w;
+        I.B = rp.B;
+        I.rad = rp.rad;
+        I.tau = rp.tau;
+        I.npk = npk[b];
+        I.res_off = plan.nres;
+        plan.nres += I.npk;
+        I.grid_off = (int64_t)plan.grid_cells;
+        plan.grid_cells += (size_t)rp.G * rp.G;
+        I.fine_off = (int64_t)plan.fine_cells;
+        plan.fine_cells += (size_t)I.npk * rp.M * rp.M;
+        I.hist_off = (int64_t)plan.hist_cells;
+        plan.hist_cells += (size_t)I.npk * rp.B;
+        const AngleTables* at = angle_tables(ctx, rp.B);
+        const int16_t* disk = disk_table(ctx, rp.G);
+        if (!at || !disk) return AORESP_ENOMEM;
+        I.disk = disk;
+        I.tc = at->tc;
+        I.ts = at->ts;
+        I.th = at->th;
+        I.ct = at->ct;
+        I.st = at->st;
+        if (I.npk > plan.max_npk) plan.max_npk = I.npk;
+        if (rp.M > plan.maxM) plan.maxM = rp.M;
+        size_t lds = (size_t)rp.B * 8 + (size_t)I.npk * rp.B * 4;
+        if (lds > 160 * 1024) return AORESP_EINVAL;
+        if (lds > hist_lds) hist_lds = lds;
+        if (n == 0) continue;
+        int bw = coarse_band_width(rp.G);
+        int nbands = (rp.G + bw - 1) / bw;
+        double per_arc = 1.42 * rp.G / (2.0 * nbands);
+        int64_t chunk = (int64_t)(kVoteTarget / per_arc);
+        chunk = (chunk + kVoteThreads - 1) / kVoteThreads * kVoteThreads;
+        if (chunk < kVoteThreads) chunk = kVoteThreads;
+        for (int mode = 0; mode < 2; ++mode)
+            for (int band = 0; band < nbands; ++band)
+                for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+                    int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+                    // central bands carry more votes: weight by the band's in-disk share
+                    double c = (band + 0.5) * bw / (double)rp.G * 2.0 - 1.0;
+                    double share = std::sqrt(std::max(0.05, 1.0 - c * c));
+                    votes.push_back({per_arc * (double)(i1 - i0) * share,
+                                     make_int4(b, mode | (band << 1), (int)i0, (int)i1)});
+                }
+        for (int64_t c0 = 0; c0 < (int64_t)rp.G * rp.G; c0 += kCellChunk) {
+            int64_t c1 = c0 + kCellChunk < (int64_t)rp.G * rp.G ? c0 + kCellChunk : (int64_t)rp.G * rp.G;
+            plan.cell_items.push_back(make_int4(b, (int)c0, (int)c1, 0));
+        }
+        for (int64_t i0 = 0; i0 < n; i0 += kCorrChunk) {
+            int64_t i1 = i0 + kCorrChunk < n ? i0 + kCorrChunk : n;
+            plan.corr_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
+        }
+    }
+    std::stable_sort(votes.begin(), votes.end(),
+                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+    plan.vote_items.reserve(votes.size());
+    for (auto& v : votes) plan.vote_items.push_back(v.second);
+    plan.N = off[ninst];
+    plan.hist_lds = hist_lds;
+    return AORESP_OK;
+}
+
+aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const float* P, const float* Q,
+                           uint8_t* masks, hipStream_t s, hipEvent_t* marks, uint32_t* grid_out, uint32_t* fine_out,
+                           uint32_t* hist_out) {
+    const int64_t N = plan.N;
+    const int ninst = (int)plan.insts.size();
+    const size_t nn = N > 0 ? (size_t)N : 1;
+    aoresp_status st;
     auto mark = [&](int k) {
         if (marks) (void)hipEventRecord(marks[k], s);
     };
-    const int G = rp.G, M = rp.M, B = rp.B;
-    aoresp_status st;
-    if ((st = b.abc.ensure((size_t)n * sizeof(float4))) != AORESP_OK) return st;
-    if ((st = b.colp.ensure((size_t)n * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = b.rowp.ensure((size_t)n * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = b.clip.ensure((size_t)n * sizeof(int32_t))) != AORESP_OK) return st;
-    if ((st = b.grid.ensure((size_t)G * G * 4)) != AORESP_OK) return st;
-    if ((st = b.fine.ensure((size_t)kMaxPeaks * (M > 0 ? M * M : 1) * 4)) != AORESP_OK) return st;
-    if ((st = b.hist.ensure((size_t)kMaxPeaks * B * 4)) != AORESP_OK) return st;
-    if ((st = b.keys.ensure(kMaxPeaks * sizeof(unsigned long long))) != AORESP_OK) return st;
-    if ((st = b.st.ensure(kMaxPeaks * sizeof(PeakState))) != AORESP_OK) return st;
-    if ((st = b.res.ensure(kMaxPeaks * sizeof(aoresp_result))) != AORESP_OK) return st;
-    if ((st = b.err.ensure(sizeof(uint32_t))) != AORESP_OK) return st;
-    const AngleTables* at = angle_tables(ctx, B);
-    const int16_t* disk = disk_table(ctx, G);
-    if (!at || !disk) return AORESP_ENOMEM;
-    ArcRecs R{b.abc.as<float4>(), b.colp.as<int4>(), b.rowp.as<int4>(), b.clip.as<int32_t>()};
-    PeakState* stt = b.st.as<PeakState>();
-    aoresp_result* res = b.res.as<aoresp_result>();
-    uint32_t* fine = b.fine.as<uint32_t>();
-    uint32_t* hist = b.hist.as<uint32_t>();
-    unsigned long long* keys = b.keys.as<unsigned long long>();
+    if ((st = w.abc.ensure(nn * sizeof(float4))) != AORESP_OK) return st;
+    if ((st = w.colp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
+    if ((st = w.rowp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
+    if ((st = w.geo.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
+    if ((st = w.grid.ensure(plan.grid_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.hist.ensure(plan.hist_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
+    if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
+    if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
+    if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
+    // instance table and work items, uploaded as one blob
+    const size_t b_inst = (size_t)ninst * sizeof(Inst);
+    const size_t o_vote = (b_inst + 255) / 256 * 256;
+    const size_t o_cell = o_vote + plan.vote_items.size() * sizeof(int4);
+    const size_t o_corr = o_cell + plan.cell_items.size() * sizeof(int4);
+    const size_t total = o_corr + plan.corr_items.size() * sizeof(int4) + 16;
+    if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
+    if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
+    char* hb = w.h_plan.as<char>();
+    std::memcpy(hb, plan.insts.data(), b_inst);
+    if (!plan.vote_items.empty())
+        std::memcpy(hb + o_vote, plan.vote_items.data(), plan.vote_items.size() * sizeof(int4));
+    if (!plan.cell_items.empty())
+        std::memcpy(hb + o_cell, plan.cell_items.data(), plan.cell_items.size() * sizeof(int4));
+    if (!plan.corr_items.empty())
+        std::memcpy(hb + o_corr, plan.corr_items.data(), plan.corr_items.size() * sizeof(int4));
+    AOR_HIP(hipMemcpyAsync(w.plan.ptr, hb, total, hipMemcpyHostToDevice, s));
+    char* db = w.plan.as<char>();
+    const Inst* insts = reinterpret_cast<const Inst*>(db);
+    const int4* vote_items = reinterpret_cast<const int4*>(db + o_vote);
+    const int4* cell_items = reinterpret_cast<const int4*>(db + o_cell);
+    const int4* corr_items = reinterpret_cast<const int4*>(db + o_corr);
+
+    ArcRecs R{w.abc.as<float4>(), w.colp.as<int4>(), w.rowp.as<int4>(), w.geo.as<int4>()};
+    PeakState* stt = w.st.as<PeakState>();
+    aoresp_result* res = w.res.as<aoresp_result>();
+    unsigned long long* keys = w.keys.as<unsigned long long>();
+    uint32_t* err = w.err.as<uint32_t>();
+    uint32_t* counter = err + 1;
 
     mark(0);
-    launch_zero_u32(b.err.as<uint32_t>(), 1, s);
-    launch_zero_u32(reinterpret_cast<uint32_t*>(keys), 2 * kMaxPeaks, s);
-    launch_zero_u32(reinterpret_cast<uint32_t*>(stt), kMaxPeaks * sizeof(PeakState) / 4, s);
-    launch_zero_u32(reinterpret_cast<uint32_t*>(res), kMaxPeaks * sizeof(aoresp_result) / 4, s);
-    launch_arc_setup(P, Q, n, G, R, s);
-    launch_zero_u32(b.grid.as<uint32_t>(), (size_t)G * G, s);
+    launch_zero_u32(err, 2, s);
+    launch_zero_u32(reinterpret_cast<uint32_t*>(keys), (size_t)plan.nres * 2, s);
+    launch_zero_u32(reinterpret_cast<uint32_t*>(stt), (size_t)plan.nres * sizeof(PeakState) / 4, s);
+    launch_zero_u32(reinterpret_cast<uint32_t*>(res), (size_t)plan.nres * sizeof(aoresp_result) / 4, s);
+    launch_arc_setup(P, Q, N, insts, ninst, R, s);
+    launch_zero_u32(w.grid.as<uint32_t>(), plan.grid_cells, s);
     mark(1);
-    launch_coarse_vote(R, n, G, disk, b.grid.as<uint32_t>(), b.err.as<uint32_t>(), coarse_chunks(ctx, n, G), s);
+    launch_vote(R, insts, vote_items, (int)plan.vote_items.size(), counter, w.grid.as<uint32_t>(), err,
+                ctx->cu_count, s);
     mark(2);
-    for (int t = 0; t < npk; ++t) {
-        launch_peak(b.grid.as<uint32_t>(), G, (int64_t)G * G, stt, t, rp.rad, keys + t, s);
-        launch_peak_finish(keys + t, G, M, rp.w, stt, t, s);
+    for (int t = 0; t < plan.max_npk; ++t) {
+        launch_peak(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), stt, t, keys, s);
+        launch_peak_finish(insts, ninst, keys, stt, t, s);
     }
     mark(3);
-    if (M > 0) launch_zero_u32(fine, (size_t)npk * M * M, s);
-    for (int t = 0; t < npk; ++t) {
-        if (M > 0) launch_fine_vote(R, n, M, stt, t, fine + (size_t)t * M * M, b.err.as<uint32_t>(), s);
-        launch_fine_peak(fine + (size_t)t * (M > 0 ? M * M : 0), G, M, stt, t, s);
+    if (plan.maxM > 0) launch_zero_u32(w.fine.as<uint32_t>(), plan.fine_cells, s);
+    for (int t = 0; t < plan.max_npk; ++t) {
+        if (plan.maxM > 0)
+            launch_fine_vote(R, insts, corr_items, (int)plan.corr_items.size(), stt, t, w.fine.as<uint32_t>(), err,
+                             plan.maxM, s);
+        launch_fine_peak(w.fine.as<uint32_t>(), insts, ninst, stt, t, s);
     }
     mark(4);
-    launch_zero_u32(hist, (size_t)npk * B, s);
-    // histograms of several peaks share one pass while the LDS allows it
-    int per = (int)((160 * 1024 - (size_t)B * 8) / ((size_t)B * 4));
-    if (per < 1) return AORESP_EINVAL;
-    for (int t0 = 0; t0 < npk; t0 += per) {
-        int cnt = npk - t0 < per ? npk - t0 : per;
-        launch_angle_hist(P, Q, n, stt + t0, cnt, B, at->tc, at->ts, hist + (size_t)t0 * B, s);
-    }
-    for (int t = 0; t < npk; ++t) launch_angle_peak(hist, B, at->th, at->ct, at->st, stt, t, G, res, s);
+    launch_zero_u32(w.hist.as<uint32_t>(), plan.hist_cells, s);
+    launch_angle_hist(P, Q, N, insts, corr_items, (int)plan.corr_items.size(), stt, w.hist.as<uint32_t>(),
+                      plan.hist_lds, s);
+    for (int t = 0; t < plan.max_npk; ++t) launch_angle_peak(w.hist.as<uint32_t>(), insts, ninst, stt, t, res, s);
     mark(5);
-    launch_inliers(P, Q, n, stt, npk, rp.tau, res, masks, s);
+    launch_inliers(P, Q, N, insts, ninst, stt, res, masks, s);
     mark(6);
-    if (grid_out)
-        AOR_HIP(hipMemcpyAsync(grid_out, b.grid.ptr, (size_t)G * G * 4, hipMemcpyDeviceToDevice, s));
-    if (fine_out && M > 0)
-        AOR_HIP(hipMemcpyAsync(fine_out, fine, (size_t)npk * M * M * 4, hipMemcpyDeviceToDevice, s));
-    if (hist_out) AOR_HIP(hipMemcpyAsync(hist_out, hist, (size_t)npk * B * 4, hipMemcpyDeviceToDevice, s));
+    if (ninst == 1) {
+        const Inst& I = plan.insts[0];
+        if (grid_out)
+            AOR_HIP(hipMemcpyAsync(grid_out, w.grid.ptr, (size_t)I.G * I.G * 4, hipMemcpyDeviceToDevice, s));
+        if (fine_out && I.M > 0)
+            AOR_HIP(hipMemcpyAsync(fine_out, w.fine.ptr, plan.fine_cells * 4, hipMemcpyDeviceToDevice, s));
+        if (hist_out) AOR_HIP(hipMemcpyAsync(hist_out, w.hist.ptr, plan.hist_cells * 4, hipMemcpyDeviceToDevice, s));
+    }
     AOR_HIP(hipGetLastError());
     return AORESP_OK;
 }
 
-aoresp_status finish_solve(DeviceCtx* ctx, int npk, aoresp_result* out, uint32_t* k_found, hipStream_t s) {
-    SolveBuffers& b = ctx->buf;
-    AOR_HIP(hipMemcpyAsync(b.h_res, b.res.ptr, sizeof(aoresp_result) * npk, hipMemcpyDeviceToHost, s));
-    AOR_HIP(hipMemcpyAsync(b.h_st, b.st.ptr, sizeof(PeakState) * npk, hipMemcpyDeviceToHost, s));
-    AOR_HIP(hipMemcpyAsync(b.h_err, b.err.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    AOR_HIP(hipStreamSynchronize(s));
-    if (*b.h_err) {
-        if (debug_on()) fprintf(stderr, "aoresp: internal check flag 0x%x\n", *b.h_err);
+aoresp_status fetch_plan(Workspace& w, const Plan& plan, hipStream_t s) {
+    aoresp_status st;
+    if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
+    if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
+    AOR_HIP(hipMemcpyAsync(w.h_res.ptr, w.res.ptr, sizeof(aoresp_result) * plan.nres, hipMemcpyDeviceToHost, s));
+    AOR_HIP(hipMemcpyAsync(w.h_st.ptr, w.st.ptr, sizeof(PeakState) * plan.nres, hipMemcpyDeviceToHost, s));
+    uint32_t* herr = reinterpret_cast<uint32_t*>(w.h_st.as<char>() + sizeof(PeakState) * plan.nres);
+    AOR_HIP(hipMemcpyAsync(herr, w.err.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    return AORESP_OK;
+}
+
+aoresp_status collect_plan(Workspace& w, const Plan& plan, aoresp_result* out, std::vector<int>& valid) {
+    const uint32_t* herr = reinterpret_cast<const uint32_t*>(w.h_st.as<char>() + sizeof(PeakState) * plan.nres);
+    if (*herr) {
+        if (debug_on()) fprintf(stderr, "aoresp: internal check flag 0x%x\n", *herr);
         return AORESP_EDEVICE;
     }
-    uint32_t found = 0;
-    for (int t = 0; t < npk; ++t) {
-        out[t] = b.h_res[t];
-        if (b.h_st[t].valid) ++found;
+    const aoresp_result* hr = w.h_res.as<aoresp_result>();
+    const PeakState* hs = w.h_st.as<PeakState>();
+    valid.assign(plan.nres, 0);
+    for (int t = 0; t < plan.nres; ++t) {
+        out[t] = hr[t];
+        valid[t] = hs[t].valid ? 1 : 0;
     }
-    if (k_found) *k_found = found;
-    return found ? AORESP_OK : AORESP_ENODATA;
+    return AORESP_OK;
+}
+
+aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, std::vector<int>& valid,
+                          hipStream_t s) {
+    aoresp_status st = fetch_plan(w, plan, s);
+    if (st != AORESP_OK) return st;
+    AOR_HIP(hipStreamSynchronize(s));
+    return collect_plan(w, plan, out, valid);
+}
+
+void release_workspace(Workspace& w) {
+    DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys,
+                      &w.st, &w.res, &w.err, &w.plan, &w.P, &w.Q, &w.masks};
+    for (DevBuf* b : bufs) b->release();
+    HostBuf* hb[] = {&w.h_plan, &w.h_res, &w.h_st};
+    for (HostBuf* b : hb) {
+        if (b->ptr) (void)hipHostFree(b->ptr);
+        b->ptr = nullptr;
+        b->bytes = 0;
+    }
 }
 
 static void identity_result(aoresp_result* r, int G) {
@@ -272,14 +406,17 @@ static void identity_result(aoresp_result* r, int G) {
     r->grid = (uint32_t)G;
 }
 
+// Single instance with k peaks on device pointers.
 static aoresp_status solve_dev_common(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
                                       aoresp_result* out, uint8_t* masks, uint32_t* k_found, uint32_t* grid_out,
-                                      uint32_t* fine_out, uint32_t* hist_out, hipStream_t s) {
+                                      uint32_t* fine_out, uint32_t* hist_out, hipStream_t s,
+                                      hipEvent_t* marks = nullptr) {
     if (!out || (n > 0 && (!P || !Q)) || k < 1 || k > (uint32_t)kMaxPeaks) return AORESP_EINVAL;
     if (n > (size_t)INT32_MAX) return AORESP_EINVAL;
     ResolvedParams rp;
     aoresp_status st = resolve_params(prm, n, rp);
     if (st != AORESP_OK) return st;
+    if ((size_t)rp.B * 8 + (size_t)k * rp.B * 4 > 160 * 1024) return AORESP_EINVAL;
     if (n < 2) {
         for (uint32_t t = 0; t < k; ++t) identity_result(&out[t], rp.G);
         if (k_found) *k_found = 0;
@@ -292,12 +429,21 @@ static aoresp_status solve_dev_common(const float* P, const float* Q, size_t n, 
     DeviceCtx* ctx = device_ctx();
     if (!ctx) return AORESP_EDEVICE;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    st = enqueue_solve(ctx, P, Q, (int64_t)n, rp, (int)k, masks, grid_out, fine_out, hist_out, s);
-    if (st != AORESP_OK) return st;
-    st = finish_solve(ctx, (int)k, out, k_found, s);
-    if (st == AORESP_ENODATA)
+    Plan plan;
+    int64_t off[2] = {0, (int64_t)n};
+    int npk = (int)k;
+    if ((st = build_plan(ctx, off, 1, &rp, &npk, plan)) != AORESP_OK) return st;
+    if ((st = enqueue_plan(ctx, ctx->ws, plan, P, Q, masks, s, marks, grid_out, fine_out, hist_out)) != AORESP_OK) return st;
+    std::vector<int> valid;
+    if ((st = finish_plan(ctx->ws, plan, out, valid, s)) != AORESP_OK) return st;
+    uint32_t found = 0;
+    while (found < k && valid[found]) ++found;
+    if (k_found) *k_found = found;
+    if (found == 0) {
         for (uint32_t t = 0; t < k; ++t) identity_result(&out[t], rp.G);
-    return st;
+        return AORESP_ENODATA;
+    }
+    return AORESP_OK;
 }
 
 static aoresp_status solve_host_common(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
@@ -307,6 +453,7 @@ static aoresp_status solve_host_common(const float* P, const float* Q, size_t n,
     ResolvedParams rp;
     aoresp_status st = resolve_params(prm, n, rp);
     if (st != AORESP_OK) return st;
+    if ((size_t)rp.B * 8 + (size_t)k * rp.B * 4 > 160 * 1024) return AORESP_EINVAL;
     if (n < 2) {
         for (uint32_t t = 0; t < k; ++t) identity_result(&out[t], rp.G);
         if (k_found) *k_found = 0;
@@ -316,23 +463,32 @@ static aoresp_status solve_host_common(const float* P, const float* Q, size_t n,
     DeviceCtx* ctx = device_ctx();
     if (!ctx) return AORESP_EDEVICE;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    SolveBuffers& b = ctx->buf;
-    hipStream_t s = b.stream;
-    if ((st = b.P.ensure(3 * n * sizeof(float))) != AORESP_OK) return st;
-    if ((st = b.Q.ensure(3 * n * sizeof(float))) != AORESP_OK) return st;
-    if (masks && (st = b.masks.ensure(n * k)) != AORESP_OK) return st;
-    AOR_HIP(hipMemcpyAsync(b.P.ptr, P, 3 * n * sizeof(float), hipMemcpyHostToDevice, s));
-    AOR_HIP(hipMemcpyAsync(b.Q.ptr, Q, 3 * n * sizeof(float), hipMemcpyHostToDevice, s));
-    st = enqueue_solve(ctx, b.P.as<float>(), b.Q.as<float>(), (int64_t)n, rp, (int)k,
-                       masks ? b.masks.as<uint8_t>() : nullptr, nullptr, nullptr, nullptr, s);
-    if (st != AORESP_OK) return st;
-    if (masks) AOR_HIP(hipMemcpyAsync(masks, b.masks.ptr, n * k, hipMemcpyDeviceToHost, s));
-    st = finish_solve(ctx, (int)k, out, k_found, s);
-    if (st == AORESP_ENODATA) {
+    Workspace& w = ctx->ws;
+    hipStream_t s = w.stream;
+    if ((st = w.P.ensure(3 * n * sizeof(float))) != AORESP_OK) return st;
+    if ((st = w.Q.ensure(3 * n * sizeof(float))) != AORESP_OK) return st;
+    if (masks && (st = w.masks.ensure(n * k)) != AORESP_OK) return st;
+    AOR_HIP(hipMemcpyAsync(w.P.ptr, P, 3 * n * sizeof(float), hipMemcpyHostToDevice, s));
+    AOR_HIP(hipMemcpyAsync(w.Q.ptr, Q, 3 * n * sizeof(float), hipMemcpyHostToDevice, s));
+    Plan plan;
+    int64_t off[2] = {0, (int64_t)n};
+    int npk = (int)k;
+    if ((st = build_plan(ctx, off, 1, &rp, &npk, plan)) != AORESP_OK) return st;
+    if ((st = enqueue_plan(ctx, ctx->ws, plan, w.P.as<float>(), w.Q.as<float>(), masks ? w.masks.as<uint8_t>() : nullptr, s)) !=
+        AORESP_OK)
+        return st;
+    if (masks) AOR_HIP(hipMemcpyAsync(masks, w.masks.ptr, n * k, hipMemcpyDeviceToHost, s));
+    std::vector<int> valid;
+    if ((st = finish_plan(ctx->ws, plan, out, valid, s)) != AORESP_OK) return st;
+    uint32_t found = 0;
+    while (found < k && valid[found]) ++found;
+    if (k_found) *k_found = found;
+    if (found == 0) {
         for (uint32_t t = 0; t < k; ++t) identity_result(&out[t], rp.G);
         if (masks) std::memset(masks, 0, n * k);
+        return AORESP_ENODATA;
     }
-    return st;
+    return AORESP_OK;
 }
 
 }  // namespace aoresp
@@ -382,48 +538,43 @@ aoresp_status aoresp_coarse_grid_dev(const float* P, const float* Q, size_t n, u
     if (!grid || (n > 0 && (!P || !Q)) || n > (size_t)INT32_MAX) return AORESP_EINVAL;
     if (!is_pow2(G) || G < 64 || G > 4096) return AORESP_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
+    if (n < 2) {
+        // fewer than two correspondences still vote: run the vote path alone
+    }
+    aoresp_params prm{};
+    prm.grid = G;
+    aoresp_result out;
+    if (n == 0) {
+        launch_zero_u32(grid, (size_t)G * G, s);
+        AOR_HIP(hipGetLastError());
+        AOR_HIP(hipStreamSynchronize(s));
+        return AORESP_OK;
+    }
+    // the full single solve writes its coarse grid into `grid`
+    ResolvedParams rp;
+    aoresp_status st = resolve_params(&prm, n, rp);
+    if (st != AORESP_OK) return st;
     DeviceCtx* ctx = device_ctx();
     if (!ctx) return AORESP_EDEVICE;
     std::lock_guard<std::mutex> lk(ctx->mu);
-    SolveBuffers& b = ctx->buf;
-    aoresp_status st;
-    size_t nn = n ? n : 1;
-    if ((st = b.abc.ensure(nn * sizeof(float4))) != AORESP_OK) return st;
-    if ((st = b.colp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = b.rowp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = b.clip.ensure(nn * sizeof(int32_t))) != AORESP_OK) return st;
-    if ((st = b.err.ensure(sizeof(uint32_t))) != AORESP_OK) return st;
-    const int16_t* disk = disk_table(ctx, (int)G);
-    if (!disk) return AORESP_ENOMEM;
-    ArcRecs R{b.abc.as<float4>(), b.colp.as<int4>(), b.rowp.as<int4>(), b.clip.as<int32_t>()};
-    launch_zero_u32(b.err.as<uint32_t>(), 1, s);
-    launch_zero_u32(grid, (size_t)G * G, s);
-    if (n) {
-        launch_arc_setup(P, Q, (int64_t)n, (int)G, R, s);
-        launch_coarse_vote(R, (int64_t)n, (int)G, disk, grid, b.err.as<uint32_t>(), coarse_chunks(ctx, n, G), s);
-    }
-    AOR_HIP(hipGetLastError());
-    AOR_HIP(hipMemcpyAsync(b.h_err, b.err.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    AOR_HIP(hipStreamSynchronize(s));
-    if (*b.h_err && debug_on()) fprintf(stderr, "aoresp: internal check flag 0x%x\n", *b.h_err);
-    return *b.h_err ? AORESP_EDEVICE : AORESP_OK;
+    Plan plan;
+    int64_t off[2] = {0, (int64_t)n};
+    int npk = 1;
+    if ((st = build_plan(ctx, off, 1, &rp, &npk, plan)) != AORESP_OK) return st;
+    if ((st = enqueue_plan(ctx, ctx->ws, plan, P, Q, nullptr, s, nullptr, grid, nullptr, nullptr)) != AORESP_OK) return st;
+    std::vector<int> valid;
+    st = finish_plan(ctx->ws, plan, &out, valid, s);
+    return st;
 }
 
 aoresp_status aoresp_stage_times_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
                                      float* ms_out, uint32_t* n_stages, void* hip_stream) {
     if (!ms_out || !n_stages || n < 2 || !P || !Q || n > (size_t)INT32_MAX) return AORESP_EINVAL;
-    ResolvedParams rp;
-    aoresp_status st = resolve_params(prm, n, rp);
-    if (st != AORESP_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;
-    DeviceCtx* ctx = device_ctx();
-    if (!ctx) return AORESP_EDEVICE;
-    std::lock_guard<std::mutex> lk(ctx->mu);
     hipEvent_t ev[kNumStages + 1];
     for (int k = 0; k <= kNumStages; ++k) AOR_HIP(hipEventCreate(&ev[k]));
-    st = enqueue_solve(ctx, P, Q, (int64_t)n, rp, 1, nullptr, nullptr, nullptr, nullptr, s, ev);
     aoresp_result tmp;
-    if (st == AORESP_OK) st = finish_solve(ctx, 1, &tmp, nullptr, s);
+    aoresp_status st = solve_dev_common(P, Q, n, 1, prm, &tmp, nullptr, nullptr, nullptr, nullptr, nullptr, s, ev);
     if (st == AORESP_OK || st == AORESP_ENODATA) {
         for (int k = 0; k < kNumStages; ++k) {
             float ms = 0.0f;

@@ -1,5 +1,9 @@
 // Internal interface between the HIP kernels (kernels.hip) and the host
 // runtime of libaoresp.  Not part of the public C ABI (include/aoresp.h).
+//
+// Every kernel works on a batch of independent instances described by an
+// instance table; a single solve is a batch of one.  Per-correspondence data
+// is indexed by global column (instance offset + local index).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stddef.h>
@@ -12,23 +16,44 @@ namespace aoresp {
 constexpr uint32_t kFlagDegenerate = 1u;  // d = 0 or non-finite: no axis vote
 constexpr uint32_t kFlagRisky = 2u;       // max |d_k| outside [2^-100, 2^120]: exhaustive cell test
 constexpr uint32_t kFlagLine = 4u;        // c == 0: the projected curve is a line
+constexpr uint32_t kFlagLineDown = 8u;    // line whose cross coordinate decreases along the scan
 
 constexpr int kMaxPeaks = 8;
 constexpr int kTileCells = 32768;         // u32 cells of one coarse LDS band (128 KiB)
+constexpr int kVoteThreads = 1024;
+constexpr int kQueueCap = 4 * kVoteThreads;
 
-// Per-correspondence records of the setup kernel (SoA, n entries each).
-//  abc : displacement (a, b, c) negated if needed so that c >= 0; .w = flags.
-//  colp: vertex-column ranges [s, e] of the four column-mode octants
-//        (lower root left / right of the bottom point, upper root left / right
-//        of the top point), each packed as int16 s | int16 e << 16.
-//  rowp: vertex-row ranges of the four row-mode octants (lower u-root below /
-//        above the left point, upper u-root below / above the right point).
-//  clip: (ja, jb): lower-u-root cells need column < ja, upper ones >= jb.
+// Per-correspondence records (SoA, one entry per global column).
+//  abc : displacement (a, b, c) negated if needed so that c >= 0; .w = the
+//        certification threshold of the walk.
+//  colp: vertex-column ranges [s, e] of the four column-mode octants, each
+//        packed as int16 s | int16 e << 16 (empty when s >= e); a risky
+//        correspondence carries kRiskyMark in colp.x.
+//  rowp: the same for the four row-mode octants.
+//  geo : (ja | jb << 16, jm | km << 16, ka | kb << 16, flags), see walker.h.
 struct ArcRecs {
     float4* abc;
     int4* colp;
     int4* rowp;
-    int32_t* clip;
+    int4* geo;
+};
+constexpr int32_t kRiskyMark = 0x7FFF7FFF;
+
+// One instance of a batch.
+struct Inst {
+    int64_t off;          // first global column
+    int32_t n;            // correspondences
+    int32_t G, M, w, B, rad, npk, res_off;
+    float tau;
+    int64_t grid_off;     // u32 offset of its G*G coarse grid in the grid arena
+    int64_t fine_off;     // u32 offset of its npk fine grids (M*M each)
+    int64_t hist_off;     // u32 offset of its npk histograms (B each)
+    const int16_t* disk;  // in-disk cross range per cell line (G pairs)
+    const float* tc;      // angle tables for B: boundary cos / sin, centre angle / cos / sin
+    const float* ts;
+    const float* th;
+    const float* ct;
+    const float* st;
 };
 
 struct FineWin {
@@ -36,7 +61,7 @@ struct FineWin {
     int nx, ny;
 };
 
-// Device-side state of one peak (axis hypothesis).
+// Device-side state of one peak (axis hypothesis); index res_off + slot.
 struct PeakState {
     int valid;
     uint32_t peak_cell, axis_votes;
@@ -45,25 +70,37 @@ struct PeakState {
     FineWin win;
 };
 
-int coarse_band_width(int G);
-size_t coarse_lds_bytes(int G);
+// Coarse LDS band width (cell lines) for a G x G grid.
+__host__ __device__ inline int coarse_band_width(int G) {
+    int bw = kTileCells / G;
+    if (bw > G) bw = G;
+    if (bw < 1) bw = 1;
+    return bw;
+}
+size_t coarse_lds_bytes();
 
 void launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
-void launch_arc_setup(const float* P, const float* Q, int64_t n, int G, ArcRecs recs, hipStream_t s);
-void launch_coarse_vote(ArcRecs recs, int64_t n, int G, const int16_t* disk, uint32_t* grid, uint32_t* err,
-                        int chunks, hipStream_t s);
-void launch_peak(const uint32_t* a, int G, int64_t count, const PeakState* prev, int prev_count, int rad,
-                 unsigned long long* key, hipStream_t s);
-void launch_peak_finish(const unsigned long long* key, int G, int M, int w, PeakState* st, int slot,
-                        hipStream_t s);
-void launch_fine_vote(ArcRecs recs, int64_t n, int M, const PeakState* st, int slot, uint32_t* fine, uint32_t* err,
+void launch_arc_setup(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, ArcRecs recs,
                       hipStream_t s);
-void launch_fine_peak(const uint32_t* fine, int G, int M, PeakState* st, int slot, hipStream_t s);
-void launch_angle_hist(const float* P, const float* Q, int64_t n, const PeakState* st, int npk, int B,
-                       const float* tc, const float* ts, uint32_t* hist, hipStream_t s);
-void launch_angle_peak(const uint32_t* hist, int B, const float* cth, const float* cct, const float* cst,
-                       PeakState* st, int slot, int G, aoresp_result* out, hipStream_t s);
-void launch_inliers(const float* P, const float* Q, int64_t n, const PeakState* st, int npk, float tau,
-                    aoresp_result* out, uint8_t* masks, hipStream_t s);
+// items: int4 (inst, mode | band << 1, i0, i1), processed by `blocks`
+// persistent work-groups pulling from *counter (must be zero on entry).
+void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, uint32_t* counter,
+                 uint32_t* grid_arena, uint32_t* err, int blocks, hipStream_t s);
+// cell items: int4 (inst, c0, c1, -); one block each.
+void launch_peak(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, const PeakState* st,
+                 int slot, unsigned long long* keys, hipStream_t s);
+void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* keys, PeakState* st, int slot,
+                        hipStream_t s);
+// correspondence items: int4 (inst, i0, i1, -); one block each.
+void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
+                      uint32_t* fine_arena, uint32_t* err, int maxM, hipStream_t s);
+void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, PeakState* st, int slot,
+                      hipStream_t s);
+void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
+                       const PeakState* st, uint32_t* hist_arena, size_t lds_bytes, hipStream_t s);
+void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,
+                       aoresp_result* res, hipStream_t s);
+void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, const PeakState* st,
+                    aoresp_result* res, uint8_t* masks, hipStream_t s);
 
 }  // namespace aoresp

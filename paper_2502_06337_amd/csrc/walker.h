@@ -1,7 +1,7 @@
 // Host/device walker of the projected circles: octant pieces of a circle in a
-// grid frame and the exact per-line transition walk.  Compiled for the GPU in
-// kernels.hip; the same functions build on the host for CPU checks of the
-// indexing (nothing on the host product path calls them).
+// grid frame and the per-line transition walk that lists the voted cells.
+// Compiled for the GPU in kernels.hip; the same functions build on the host so
+// the indexing can be checked on a CPU (no host product path calls them).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -12,10 +12,6 @@
 
 namespace aoresp {
 
-// --------------------------------------------------------------------------
-// Octant pieces of one circle in one grid frame
-// --------------------------------------------------------------------------
-
 AOR_HD __forceinline__ int clamp_index(double t, int lo, int hi) {
     if (!(t > (double)lo)) return lo;   // also catches NaN
     if (t > (double)hi) return hi;
@@ -25,8 +21,8 @@ AOR_HD __forceinline__ int clamp_index(double t, int lo, int hi) {
 // Restrict a monotone octant [s, e] (vertex indices along x) to the vertex
 // lines where its crossing lies in [ylo, yhi].  side selects the along-root
 // (0: smaller, 1: larger) when solving for x at a given cross value.
-AOR_HD void clip_octant(double aL, double bL, double c, int sel, int side, double x0, double hx,
-                            double ylo, double yhi, int nmax, int& s, int& e) {
+AOR_HD inline void clip_octant(double aL, double bL, double c, int sel, int side, double x0, double hx, double ylo,
+                               double yhi, int nmax, int& s, int& e) {
     if (s >= e) return;
     double xs = x0 + s * hx, xe = x0 + e * hx;
     double ys = cross_root(aL, bL, c, xs, sel), ye = cross_root(aL, bL, c, xe, sel);
@@ -47,18 +43,39 @@ AOR_HD void clip_octant(double aL, double bL, double c, int sel, int side, doubl
     if (e < s) e = s;
 }
 
-// Pieces of the curve of (a, b, c) (c >= 0, not degenerate, not risky) in the
-// frame u = u0 + j*hu (j in [0, nu]), v = v0 + k*hv (k in [0, nv]).
-// colp: vertex-column ranges of the column-mode octants (lower root left /
-// right of the bottom point, upper root left / right of the top point).
-// rowp: vertex-row ranges of the row-mode octants (lower u-root below / above
-// the left point, upper u-root below / above the right point), extended by 3
-// rows past the 45-degree points so that the cells around those points are
-// owned by exactly one piece.  clip = (ja, jb): lower-u-root cells must have
-// column < ja, upper-u-root cells column >= jb.
-AOR_HD void circle_pieces(float af, float bf, float cf, bool line, double u0, double hu, int nu,
-                              double v0, double hv, int nv, double margin, int4& colp, int4& rowp,
-                              int32_t& clip) {
+AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
+    if (!(isfinite(a) && isfinite(b) && isfinite(c))) return kFlagDegenerate;
+    if (a == 0.0f && b == 0.0f && c == 0.0f) return kFlagDegenerate;
+    float m = fmaxf(fabsf(a), fmaxf(fabsf(b), fabsf(c)));
+    if (m < 0x1p-100f || m > 0x1p120f) return kFlagRisky;
+    if (c == 0.0f) return kFlagLine;
+    return 0u;
+}
+
+// Certification threshold of the walk: a vertex with sigma*F > T lies below
+// the curve by at least 2.3e-6 in the cross direction (and above for < -T).
+AOR_HD __forceinline__ float cert_threshold(float a, float b, float c) {
+    return 1e-5f * ((fabsf(a) + fabsf(b)) + fabsf(c));
+}
+
+// Octant pieces of the curve of (a, b, c) (c >= 0; not degenerate, not risky)
+// in the frame u = u0 + j*hu (j in [0, nu]), v = v0 + k*hv (k in [0, nv]).
+//
+// The circle is cut at its 45-degree points: the top and bottom quarters
+// (|dv/du| <= 1) are scanned along vertex columns, the left and right
+// quarters (|du/dv| <= 1) along vertex rows.  Each quarter is split at its
+// extreme point into two monotone octants.  Octant p of a quarter:
+//   colp: p = 0 lower root left of the bottom point, 1 lower root right of it,
+//         2 upper root left of the top point, 3 upper root right of it;
+//   rowp: p = 0 lower u-root below the left point, 1 above it, 2 upper u-root
+//         below the right point, 3 above it.
+// Cells are owned by exactly one piece: column pieces own cell columns
+// [ja, jb); row pieces own rows [ka - 3, kb + 3) but only columns < ja (lower
+// u-root) or >= jb (upper u-root); the 3 extra rows cover the cells around the
+// 45-degree points.  geo = (ja | jb << 16, jm | km << 16, ka | kb << 16, flags)
+// with jm, km the lines just before the extreme points.
+AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, double u0, double hu, int nu,
+                                 double v0, double hv, int nv, double margin, int4& colp, int4& rowp, int4& geo) {
     const int E = pack_range(0, 0);
     colp = make_int4(E, E, E, E);
     rowp = make_int4(E, E, E, E);
@@ -66,9 +83,10 @@ AOR_HD void circle_pieces(float af, float bf, float cf, bool line, double u0, do
     double ulo = u0 - margin, uhi = u0 + nu * hu + margin;
     double vlo = v0 - margin, vhi = v0 + nv * hv + margin;
     int s, e;
-    if (line) {
-        // One monotone piece: column mode if |slope| <= 1, else row mode; below
+    if (flags & kFlagLine) {
+        // One straight piece: column mode if |slope| <= 1, else row mode.  Below
         // (left of) the line sigma*F > 0 with sigma = -sign(b) (-sign(a)).
+        uint32_t fl = flags;
         if (fabs(a) <= fabs(b)) {
             s = 0;
             e = nu;
@@ -77,7 +95,8 @@ AOR_HD void circle_pieces(float af, float bf, float cf, bool line, double u0, do
             if (e > nu) e = nu;
             int32_t pr = pack_range(s, e > s ? e : s);
             if (b < 0.0) colp.x = pr; else colp.z = pr;
-            clip = pack_range(0, nu);
+            if (a * b > 0.0) fl |= kFlagLineDown;   // v = -(a/b) u decreases
+            geo = make_int4(pack_range(-8, nu + 8), pack_range(nu + 8, 0), pack_range(-8, nv + 8), (int)fl);
         } else {
             s = 0;
             e = nv;
@@ -86,7 +105,9 @@ AOR_HD void circle_pieces(float af, float bf, float cf, bool line, double u0, do
             if (e > nv) e = nv;
             int32_t pr = pack_range(s, e > s ? e : s);
             if (a < 0.0) rowp.x = pr; else rowp.z = pr;
-            clip = pack_range(nu, 0);
+            if (a * b > 0.0) fl |= kFlagLineDown;   // u = -(b/a) v decreases
+            // every column allowed for either root; strict everywhere
+            geo = make_int4(pack_range(nu + 8, -8), pack_range(nu + 8, nv + 8), pack_range(-8, nv + 8), (int)fl);
         }
         return;
     }
@@ -104,7 +125,6 @@ AOR_HD void circle_pieces(float af, float bf, float cf, bool line, double u0, do
     if (kb < ka) kb = ka;
     int jm = clamp_index(floor((cu - u0) / hu), ja, jb);
     int km = clamp_index(floor((cv - v0) / hv), ka, kb);
-    // column-mode octants: along = u, cross = v
     int cs[4] = {ja, jm, ja, jm}, ce[4] = {jm, jb, jm, jb};
     int32_t cp[4];
     for (int p = 0; p < 4; ++p) {
@@ -116,7 +136,6 @@ AOR_HD void circle_pieces(float af, float bf, float cf, bool line, double u0, do
         cp[p] = pack_range(s, e > s ? e : s);
     }
     colp = make_int4(cp[0], cp[1], cp[2], cp[3]);
-    // row-mode octants: along = v, cross = u
     int rs[4] = {ka - 3, km, ka - 3, km}, re[4] = {km, kb + 3, km, kb + 3};
     int32_t rp[4];
     for (int p = 0; p < 4; ++p) {
@@ -128,16 +147,32 @@ AOR_HD void circle_pieces(float af, float bf, float cf, bool line, double u0, do
         rp[p] = pack_range(s, e > s ? e : s);
     }
     rowp = make_int4(rp[0], rp[1], rp[2], rp[3]);
-    clip = pack_range(ja, jb);
+    geo = make_int4(pack_range(ja, jb), pack_range(jm, km), pack_range(ka, kb), (int)flags);
 }
 
-AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
-    if (!(isfinite(a) && isfinite(b) && isfinite(c))) return kFlagDegenerate;
-    if (a == 0.0f && b == 0.0f && c == 0.0f) return kFlagDegenerate;
-    float m = fmaxf(fabsf(a), fmaxf(fabsf(b), fabsf(c)));
-    if (m < 0x1p-100f || m > 0x1p120f) return kFlagRisky;
-    if (c == 0.0f) return kFlagLine;
-    return 0u;
+// Direction of the transition index along octant p (+1 grows, -1 shrinks) and
+// the vertex lines [lo, hi] on which the octant is monotone with |slope| <= 1.
+AOR_HD __forceinline__ void octant_walk_info(int mode, int p, const int4& geo, int& dir, int& slo, int& shi) {
+    int ja, jb, jm, km, ka, kb;
+    unpack_range(geo.x, ja, jb);
+    unpack_range(geo.y, jm, km);
+    unpack_range(geo.z, ka, kb);
+    uint32_t fl = (uint32_t)geo.w;
+    if (fl & kFlagLine) {
+        dir = (fl & kFlagLineDown) ? -1 : 1;
+        slo = -(1 << 20);
+        shi = 1 << 20;
+        return;
+    }
+    // column octants: 0 falls, 1 rises, 2 rises, 3 falls; the same for rows
+    dir = (p == 0 || p == 3) ? -1 : 1;
+    if (mode == 0) {
+        slo = (p & 1) ? jm + 1 : ja;
+        shi = (p & 1) ? jb : jm;
+    } else {
+        slo = (p & 1) ? km + 1 : ka;
+        shi = (p & 1) ? kb : km;
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -146,22 +181,29 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
 
 constexpr int kMaxSteps = 24;
 
-// lo = first vertex (upward from g) with sigma*F <= 0, hi = last with
-// sigma*F >= 0, given the sign pattern "+ ... + [0] - ... -" near g.
-AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float ax, float y0, float hy,
-                                                int g, int& lo, int& hi, uint32_t& bad) {
+// Exact search from vertex g: lo = first vertex with sigma*F <= 0, hi = last
+// with sigma*F >= 0, for the pattern "+ ... + [0] - ... -" around the crossing.
+// flo / fhi return sigma*F at lo and hi when hi == lo - 1 (no zero).
+AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float ax, float y0, float hy, int g,
+                                            int& lo, int& hi, float& flo, float& fhi, uint32_t& bad) {
     int k = g;
     float y = y0 + (float)k * hy;
     float f = vertex_F(sb, sc, xx, ax, y);
+    float fprev = f;
     int steps = 0;
+    flo = 0.0f;
+    fhi = 0.0f;
     if (f > 0.0f) {
         do {
+            fprev = f;
             ++k;
             y += hy;
             f = vertex_F(sb, sc, xx, ax, y);
         } while (f > 0.0f && ++steps < kMaxSteps);
         lo = k;
         hi = k - 1;
+        flo = f;
+        fhi = fprev;
         if (!(f < 0.0f)) {
             if (f > 0.0f) bad = 1u;
             while (steps++ < kMaxSteps) {
@@ -173,12 +215,15 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
         }
     } else if (f < 0.0f) {
         do {
+            fprev = f;
             --k;
             y -= hy;
             f = vertex_F(sb, sc, xx, ax, y);
         } while (f < 0.0f && ++steps < kMaxSteps);
         hi = k;
         lo = k + 1;
+        fhi = f;
+        flo = fprev;
         if (!(f > 0.0f)) {
             if (f < 0.0f) bad = 1u;
             while (steps++ < kMaxSteps) {
@@ -209,33 +254,63 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
     }
 }
 
-// Walk one octant piece over cell lines [cs, ce) of a frame.  emit(j, klo, khi)
-// receives the voted cross range of cell line j (before clipping).
+// Walk octant cells [cs, ce) of a frame.  The voted cells of cell line j are
+// cross indices min(lo_j, lo_j+1) - 1 .. max(hi_j, hi_j+1), handed to
+// emit(j, klo, khi) (unclipped).
+//
+// Certified step (one evaluation per line): on lines where the octant is
+// monotone with |slope| <= 1 the transition moves by at most one index per
+// line in direction dir.  If line j's bracketing vertices (lo-1 below, lo
+// above) are certified (|sigma*F| > T), then on line j+1 only the vertex in
+// the direction of motion needs evaluating: a certified sign there decides
+// whether the transition moved, and the other bracketing vertex inherits its
+// certificate because its cross distance to the curve can only grow.  Any
+// uncertain value (|sigma*F| <= T, zeros included) falls back to the exact
+// search, which is also used for the first line of the walk.
 template <class Emit>
-AOR_HD __forceinline__ void walk_piece(float aL, float bL, float c, int sel, float x0, float hx, float y0,
-                                           float hy, int cs, int ce, Emit& emit, uint32_t& bad) {
+AOR_HD __forceinline__ void walk_octant(float aL, float bL, float c, int sel, int dir, int slo, int shi, float T,
+                                        float x0, float hx, float y0, float hy, int cs, int ce, Emit& emit,
+                                        uint32_t& bad) {
     float sigma = sel ? -1.0f : 1.0f;
     double xr = (double)x0 + (double)cs * (double)hx;
     double yr = cross_root(aL, bL, c, xr, sel);
     double gt = floor((yr - (double)y0) / (double)hy);
-    int g = clamp_index(gt, -8, 1 << 14);
+    int g = clamp_index(gt, -16, 1 << 14);
     float sa = sigma * aL, sb = sigma * bL, sc = sigma * c;
     float x = x0 + (float)cs * hx;
     float xx = x * x, ax = sa * x;
-    int lo0, hi0, lo1, hi1;
-    find_transition(sb, sc, xx, ax, y0, hy, g, lo0, hi0, bad);
+    int lo, hi;
+    float flo, fhi;
+    find_transition(sb, sc, xx, ax, y0, hy, g, lo, hi, flo, fhi, bad);
+    bool cert = (hi == lo - 1) && (flo < -T) && (fhi > T);
+    const int off = dir < 0 ? 1 : 0;   // evaluated vertex: lo (rising) or lo - 1 (falling)
     for (int j = cs; j < ce; ++j) {
         x += hx;
         xx = x * x;
         ax = sa * x;
-        find_transition(sb, sc, xx, ax, y0, hy, lo0, lo1, hi1, bad);
-        int rlo = (lo0 < lo1 ? lo0 : lo1) - 1;
-        int rhi = hi0 > hi1 ? hi0 : hi1;
-        emit(j, rlo, rhi);
-        lo0 = lo1;
-        hi0 = hi1;
+        int lo1, hi1;
+        bool fast = cert && j >= slo && j + 1 <= shi;
+        float f = 0.0f;
+        if (fast) {
+            float y = y0 + (float)(lo - off) * hy;
+            f = vertex_F(sb, sc, xx, ax, y);
+            fast = (f > T) || (f < -T);
+        }
+        if (fast) {
+            // rising: below -> lo + 1; falling: above -> lo - 1
+            bool moved = dir > 0 ? (f > T) : (f < -T);
+            lo1 = moved ? lo + dir : lo;
+            hi1 = lo1 - 1;
+        } else {
+            find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo, fhi, bad);
+            cert = (hi1 == lo1 - 1) && (flo < -T) && (fhi > T);
+        }
+        int klo = (lo < lo1 ? lo : lo1) - 1;
+        int khi = hi > hi1 ? hi : hi1;
+        emit(j, klo, khi);
+        lo = lo1;
+        hi = hi1;
     }
 }
-
 
 }  // namespace aoresp

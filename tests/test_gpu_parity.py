@@ -156,3 +156,62 @@ def test_enodata(aor):
     r, m, st = aor.est_rotation(P, P, aor.SolveParams(grid=64))
     assert st == aor.ENODATA
     assert np.array_equal(r["R"], np.eye(3, dtype=np.float32))
+
+
+# ------------------------------------------------------------------ batching
+def test_batch_matches_single_solves(aor, orc):
+    """Instances of uneven size in one batched call: each result is
+    bit-identical to the one-at-a-time solve, and to the oracle."""
+    sizes = [1500, 0, 700, 1, 3000, 2, 900, 4100]
+    insts = [synth.make_instance(n, 500 + t, outlier_rate=0.8) for t, n in enumerate(sizes)]
+    P = np.concatenate([i.P for i in insts], axis=1)
+    Q = np.concatenate([i.Q for i in insts], axis=1)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    prms = [aor.SolveParams(grid=(128 if t % 2 else 0), angle_bins=360, refine_grid=(16 if t % 3 == 0 else 0))
+            for t in range(len(sizes))]
+    outs, mask, st = aor.est_rotation_batch(P, Q, off, prms)
+    outs_d, mask_d, st_d = aor.est_rotation_batch(dev(P), dev(Q), off, prms)
+    assert np.array_equal(mask, mask_d.cpu().numpy())
+    for t, n in enumerate(sizes):
+        assert_result_equal(outs[t], outs_d[t])
+        if n < 2:
+            assert np.array_equal(outs[t]["R"], np.eye(3, dtype=np.float32))
+            continue
+        r1, m1, _ = aor.est_rotation(insts[t].P, insts[t].Q, prms[t])
+        assert_result_equal(outs[t], r1)
+        assert np.array_equal(mask[off[t]:off[t + 1]], m1)
+        G = prms[t].grid or aor.grid_for_n(n)
+        r_or = orc.solve(insts[t].P, insts[t].Q, G=G, B=360, M=prms[t].refine_grid)
+        assert_result_equal(outs[t], r_or)
+
+
+# ------------------------------------------------------ full size, sampled
+def test_paper_scale_sampled_parity(aor, orc):
+    """n = 1e6, G = 1024 + 64x64 refinement, B = 3600 (the benchmark's launch
+    configuration): sampled coarse and fine cells recomputed by the oracle one
+    by one, the full histogram, axis, R and mask against the oracle."""
+    n, G, M, B = 1_000_000, 1024, 64, 3600
+    inst = synth.make_instance(n, 2000)
+    prm = aor.SolveParams(grid=G, refine_grid=M, angle_bins=B)
+    out = aor.solve_debug(dev(inst.P), dev(inst.Q), prm)
+    r = out["result"]
+    grid = out["grid"].cpu().numpy().view(np.uint32)
+    # the peak is the argmax of the returned grid (ties to the lowest index)
+    assert r["peak_cell"] == int(np.argmax(grid.ravel())) and r["axis_votes"] == int(grid.max())
+    rng = np.random.default_rng(7)
+    ix, iy = r["peak_cell"] % G, r["peak_cell"] // G
+    cells = [(ix + dx, iy + dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1)]
+    cells += [tuple(int(v) for v in rng.integers(0, G, 2)) for _ in range(12)]
+    for (cx, cy) in cells:
+        assert grid[cy, cx] == orc.coarse_cell(inst.P, inst.Q, G, cx, cy), (cx, cy)
+    win = orc.fine_window(G, M, 1, ix, iy)
+    fine = out["fine"].cpu().numpy().view(np.uint32)
+    fc = r["fine_cell"]
+    assert fc == int(np.argmax(fine.ravel()))
+    for (jx, jy) in [(fc % M, fc // M)] + [tuple(int(v) for v in rng.integers(0, M, 2)) for _ in range(6)]:
+        assert fine[jy, jx] == orc.fine_cell(inst.P, inst.Q, win, jx, jy), (jx, jy)
+    fin = orc.finish_peak(inst.P, inst.Q, G, M, 1, B, 0.05, r["peak_cell"], r["axis_votes"], want_grids=True)
+    assert np.array_equal(out["hist"].cpu().numpy().view(np.uint32), fin["hist"])
+    assert_result_equal(r, fin)
+    assert np.array_equal(out["mask"].cpu().numpy(), fin["mask"])
+    assert orc.rotation_error_deg(inst.R_gt[0], r["R"]) < 0.5

@@ -1,0 +1,105 @@
+"""Request loop: continuous batching on the GPU.
+
+Requests of mixed size submitted from several threads at staggered times
+are admitted while others run; each result must be bit-identical to the
+same problem solved alone with est_rotation.
+"""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2502_06337_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def aor():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_06337_amd as aor
+    aor.load_library()
+    return aor
+
+
+def same(a, b):
+    for k in ("peak_cell", "axis_votes", "fine_cell", "angle_bin", "angle_votes", "n_inliers", "grid"):
+        if a[k] != b[k]:
+            return False
+    return np.array_equal(a["R"].view(np.uint32), b["R"].view(np.uint32))
+
+
+def test_served_results_equal_solo(aor):
+    rng = np.random.default_rng(3)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(300), np.log(30000), 40))] + [0, 1, 5]
+    probs = [synth.make_instance(n, 9000 + t, outlier_rate=0.85) for t, n in enumerate(sizes)]
+    prm = aor.SolveParams(angle_bins=360, refine_grid=16)
+    srv = aor.Server(hbm_budget_bytes=64 << 20, max_slots=8)
+    ids = [None] * len(probs)
+
+    def client(lo, hi):
+        for t in range(lo, hi):
+            ids[t] = srv.submit(probs[t].P, probs[t].Q, prm)
+            time.sleep(0.001 * (t % 3))
+
+    th = [threading.Thread(target=client, args=(k, min(k + 11, len(probs)))) for k in range(0, len(probs), 11)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    served = []
+    for t, rid in enumerate(ids):
+        st, res, mask = srv.poll(rid, timeout_us=-1)
+        served.append((st, res, mask))
+    stats = srv.stats()
+    srv.close()
+    assert stats["completed"] == len(probs)
+    assert 0 < stats["p50_us"] <= stats["p99_us"]
+    for t, p in enumerate(probs):
+        st, res, mask = served[t]
+        if p.n < 2:
+            assert st == aor.ENODATA
+            continue
+        r1, m1, st1 = aor.est_rotation(p.P, p.Q, prm)
+        assert st == st1
+        assert same(res, r1), t
+        assert np.array_equal(mask, m1)
+
+
+def test_request_larger_than_budget_rejected(aor):
+    srv = aor.Server(hbm_budget_bytes=1 << 20, max_slots=4)
+    p = synth.make_instance(50000, 1)
+    with pytest.raises(aor.AorespError) as e:
+        srv.submit(p.P, p.Q, aor.SolveParams(grid=256))
+    assert e.value.status == aor.ENOMEM
+    q = synth.make_instance(500, 2)
+    rid = srv.submit(q.P, q.Q, aor.SolveParams(grid=64))
+    st, res, mask = srv.poll(rid, timeout_us=-1)
+    assert st in (aor.OK, aor.ENODATA)
+    srv.close()
+
+
+def test_poll_nonblocking_and_unknown_id(aor):
+    srv = aor.Server()
+    p = synth.make_instance(200000, 4)
+    rid = srv.submit(p.P, p.Q, aor.SolveParams(grid=1024, angle_bins=3600))
+    st, _, _ = srv.poll(rid, timeout_us=0)
+    assert st in (aor.EBUSY, aor.OK)
+    if st == aor.EBUSY:
+        st, res, _ = srv.poll(rid, timeout_us=-1)
+        assert st == aor.OK
+    st, _, _ = srv.poll(123456789, timeout_us=0)
+    assert st == aor.EINVAL
+    srv.close()
+
+
+def test_destroy_drains_queue(aor):
+    srv = aor.Server(max_slots=2)
+    ps = [synth.make_instance(5000, 70 + t) for t in range(6)]
+    ids = [srv.submit(p.P, p.Q, aor.SolveParams(grid=128)) for p in ps]
+    st, _, _ = srv.poll(ids[0], timeout_us=-1)
+    assert st == aor.OK
+    srv.close()   # the rest are drained before the loop exits
