@@ -141,7 +141,7 @@ def main() -> int:
                    "n": args.n, "grid": G, "refine": M, "angle_bins": B, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
-                     "kernel": "k_vote_bands", "kernel_ms": round(stage_avg[1], 4), "votes": votes,
+                     "kernel": "k_vote", "kernel_ms": round(stage_avg[1], 4), "votes": votes,
                      "ops_per_vote": OPS_PER_VOTE},
         "cpu_baseline": cpu,
         "stages_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_avg)},

@@ -22,7 +22,7 @@
 // so every vertex farther than E/|d| < 1e-6 from the curve gets the sign of
 // the real F.  The circle is split at its four 45-degree points: on the top
 // and bottom quarters |dv/du| <= 1 and on the left and right quarters
-// |du/dv| <= 1.  Scanning a quarter across the vertex lines it crosses at 45
+// |du/dv| <= 1 (in grid-index units).  Scanning a quarter across the vertex lines it crosses at 45
 // degrees or steeper, at most one vertex per line lies within 1.5e-6 of the
 // crossing (grid steps are >= 1.5e-5), so along each line the signs read
 // "+ ... +, at most one zero, - ... -" around the crossing.  With lo = first

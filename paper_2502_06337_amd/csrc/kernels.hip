@@ -101,13 +101,13 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                                                        uint32_t* __restrict__ grid_arena,
                                                        uint32_t* __restrict__ err) {
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ uint32_t qcount, rcount;
+    __shared__ uint32_t qcount, wcount, rcount;
     __shared__ int item_id;
     const int tid = threadIdx.x;
     uint32_t* tile = smem;
     uint16_t* queue = reinterpret_cast<uint16_t*>(smem + kTileCells);
     uint16_t* risky = queue + kQueueCap;
-    int16_t* dlim = reinterpret_cast<int16_t*>(risky + kVoteThreads);   // 2 per band line (<= 4096 lines)
+    int16_t* dlim = reinterpret_cast<int16_t*>(risky + kVoteThreads);   // 2 per band line
     uint32_t bad = 0;
 
     for (;;) {
@@ -134,52 +134,79 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         for (int64_t b0 = wi.z; b0 < wi.w; b0 += kVoteThreads) {
             if (tid == 0) {
                 qcount = 0u;
+                wcount = 0u;
                 rcount = 0u;
             }
             __syncthreads();
             int64_t li = b0 + tid;
             if (li < wi.w) {
-                int4 pc = mode == 0 ? R.colp[base0 + li] : R.rowp[base0 + li];
+                const int64_t gi = base0 + li;
+                int4 pc = mode == 0 ? R.colp[gi] : R.rowp[gi];
                 if (pc.x == kRiskyMark) {
                     if (mode == 0) risky[atomicAdd(&rcount, 1u)] = (uint16_t)tid;
                 } else {
                     int32_t pcs[4] = {pc.x, pc.y, pc.z, pc.w};
+                    bool any = false;
 #pragma unroll
                     for (int p = 0; p < 4; ++p) {
                         int s, e;
                         unpack_range(pcs[p], s, e);
-                        int cs = max(s, band0);
-                        int ce = min(e, band0 + bwb);
-                        if (cs < ce) queue[atomicAdd(&qcount, 1u)] = (uint16_t)((tid << 2) | p);
+                        any |= max(s, band0) < min(e, band0 + bwb);
+                    }
+                    if (any) {
+                        const int4 geo = R.geo[gi];
+#pragma unroll
+                        for (int p = 0; p < 4; ++p) {
+                            int s, e;
+                            unpack_range(pcs[p], s, e);
+                            int cs = max(s, band0);
+                            int ce = min(e, band0 + bwb);
+                            if (cs >= ce) continue;
+                            int dir, slo, shi;
+                            octant_walk_info(mode, p, geo, dir, slo, shi);
+                            int2 parts[3];
+                            split_piece(cs, ce, slo, shi, parts);
+                            // certified bodies from the front, searched lines from the back
+                            if (parts[1].x < parts[1].y) queue[atomicAdd(&qcount, 1u)] = (uint16_t)((tid << 4) | (p << 2) | 1);
+                            if (parts[0].x < parts[0].y) queue[kQueueCap - 1 - atomicAdd(&wcount, 1u)] = (uint16_t)((tid << 4) | (p << 2) | 0);
+                            if (parts[2].x < parts[2].y) queue[kQueueCap - 1 - atomicAdd(&wcount, 1u)] = (uint16_t)((tid << 4) | (p << 2) | 2);
+                        }
                     }
                 }
             }
             __syncthreads();
             const int qn = (int)qcount;
-            for (int t = tid; t < qn; t += kVoteThreads) {
-                const int ent = queue[t];
-                const int64_t gi = base0 + b0 + (ent >> 2);
-                const int p = ent & 3;
+            const int wn = (int)wcount;
+            for (int t = tid; t < qn + wn; t += kVoteThreads) {
+                const int ent = t < qn ? queue[t] : queue[kQueueCap - 1 - (t - qn)];
+                const int64_t gi = base0 + b0 + (ent >> 4);
+                const int p = (ent >> 2) & 3;
+                const int part = ent & 3;
                 const float4 abc = R.abc[gi];
                 const int4 pc = mode == 0 ? R.colp[gi] : R.rowp[gi];
                 const int4 geo = R.geo[gi];
                 const int32_t pr = p == 0 ? pc.x : (p == 1 ? pc.y : (p == 2 ? pc.z : pc.w));
                 int s, e;
                 unpack_range(pr, s, e);
-                const int cs = max(s, band0);
-                const int ce = min(e, band0 + bwb);
                 int dir, slo, shi;
                 octant_walk_info(mode, p, geo, dir, slo, shi);
+                int2 parts[3];
+                split_piece(max(s, band0), min(e, band0 + bwb), slo, shi, parts);
+                const int cs = parts[part].x, ce = parts[part].y;
                 const int sel = p >> 1;
                 CoarseEmit em{tile, dlim, mode, band0, bwb, G, 0, G - 1};
+                float aL = abc.x, bL = abc.y;
                 if (mode == 1) {
                     int ja, jb;
                     unpack_range(geo.x, ja, jb);
                     if (sel == 0) em.chi = min(G - 1, ja - 1); else em.clo = max(0, jb);
-                    walk_octant(abc.y, abc.x, abc.z, sel, dir, slo, shi, abc.w, -1.0f, h, -1.0f, h, cs, ce, em, bad);
-                } else {
-                    walk_octant(abc.x, abc.y, abc.z, sel, dir, slo, shi, abc.w, -1.0f, h, -1.0f, h, cs, ce, em, bad);
+                    aL = abc.y;
+                    bL = abc.x;
                 }
+                if (part == 1)
+                    walk_certified(aL, bL, abc.z, sel, dir, abc.w, -1.0f, h, -1.0f, h, cs, ce, em, bad);
+                else
+                    walk_search(aL, bL, abc.z, sel, -1.0f, h, -1.0f, h, cs, ce, em, bad);
             }
             if (mode == 0) {
                 // exhaustive cell test for correspondences outside the walk's range of validity
@@ -223,7 +250,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         }
         __syncthreads();
     }
-    if (bad) atomicOr(err, 1u);
+    if (bad) atomicOr(err, bad);
 }
 
 // --------------------------------------------------------------------------
@@ -436,30 +463,33 @@ __global__ __launch_bounds__(256) void k_fine_vote(const ArcRecs R, const Inst* 
         int32_t rps[4] = {rowp.x, rowp.y, rowp.z, rowp.w};
         int ja, jb;
         unpack_range(geo.x, ja, jb);
-        for (int p = 0; p < 4; ++p) {
-            int s0, e0, dir, slo, shi;
-            unpack_range(cps[p], s0, e0);
-            if (s0 >= e0) continue;
-            octant_walk_info(0, p, geo, dir, slo, shi);
-            em.mode = 0;
-            em.clo = -(1 << 20);
-            em.chi = 1 << 20;
-            walk_octant(abc.x, abc.y, abc.z, p >> 1, dir, slo, shi, abc.w, fw.U0, fw.hx, fw.V0, fw.hy, s0, e0, em,
-                        bad);
-        }
-        for (int p = 0; p < 4; ++p) {
-            int s0, e0, dir, slo, shi;
-            unpack_range(rps[p], s0, e0);
-            if (s0 >= e0) continue;
-            octant_walk_info(1, p, geo, dir, slo, shi);
-            em.mode = 1;
-            em.clo = (p >> 1) ? jb : -(1 << 20);
-            em.chi = (p >> 1) ? (1 << 20) : ja - 1;
-            walk_octant(abc.y, abc.x, abc.z, p >> 1, dir, slo, shi, abc.w, fw.V0, fw.hy, fw.U0, fw.hx, s0, e0, em,
-                        bad);
+        for (int m = 0; m < 2; ++m) {
+            const int32_t* pcs = m == 0 ? cps : rps;
+            for (int p = 0; p < 4; ++p) {
+                int s0, e0, dir, slo, shi;
+                unpack_range(pcs[p], s0, e0);
+                if (s0 >= e0) continue;
+                octant_walk_info(m, p, geo, dir, slo, shi);
+                em.mode = m;
+                em.clo = (m == 1 && (p >> 1)) ? jb : -(1 << 20);
+                em.chi = (m == 1 && !(p >> 1)) ? ja - 1 : (1 << 20);
+                int2 parts[3];
+                split_piece(s0, e0, slo, shi, parts);
+                float aL = m == 0 ? abc.x : abc.y, bL = m == 0 ? abc.y : abc.x;
+                float x0 = m == 0 ? fw.U0 : fw.V0, hx = m == 0 ? fw.hx : fw.hy;
+                float y0 = m == 0 ? fw.V0 : fw.U0, hy = m == 0 ? fw.hy : fw.hx;
+                for (int q = 0; q < 3; ++q) {
+                    if (parts[q].x >= parts[q].y) continue;
+                    if (q == 1)
+                        walk_certified(aL, bL, abc.z, p >> 1, dir, abc.w, x0, hx, y0, hy, parts[q].x, parts[q].y, em,
+                                       bad);
+                    else
+                        walk_search(aL, bL, abc.z, p >> 1, x0, hx, y0, hy, parts[q].x, parts[q].y, em, bad);
+                }
+            }
         }
     }
-    if (bad) atomicOr(err, 2u);
+    if (bad) atomicOr(err, bad << 8);
     __syncthreads();
     uint32_t* fine = fine_arena + I.fine_off + (size_t)slot * M * M;
     for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
@@ -747,8 +777,8 @@ __global__ void k_zero_u32(uint32_t* p, size_t count) {
 // --------------------------------------------------------------------------
 
 size_t coarse_lds_bytes() {
-    // tile + queue (u16) + risky list (u16) + in-disk limits (2 x int16 per band line)
-    return (size_t)kTileCells * 4 + kQueueCap * 2 + kVoteThreads * 2 + 2 * 2 * 4096;
+    // tile + queue (u16) + risky list (u16) + in-disk limits (2 x int16 per band line, <= 256 lines)
+    return (size_t)kTileCells * 4 + kQueueCap * 2 + kVoteThreads * 2 + 2 * 2 * 256;
 }
 
 static void set_lds_limit(const void* fn) {

@@ -52,18 +52,24 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
     return 0u;
 }
 
-// Certification threshold of the walk: a vertex with sigma*F > T lies below
-// the curve by at least 2.3e-6 in the cross direction (and above for < -T).
+// Certification threshold of the walk, T = 8e-6 (|a| + |b| + |c|).  With the
+// binary32 error bound E <= 2^-21 (|a| + |b| + |c|) (plus 2^-22 |c| for the
+// rounded W of a refinement grid), sigma*F > T puts a vertex below the curve
+// by a cross gap of at least (T - E) / (4 |d|) >= 1.7e-6, and a vertex whose
+// cross gap is at least that, on a curve of slope <= 1, is farther than
+// 1.2e-6 from it, where binary32 already gets the sign right.
 AOR_HD __forceinline__ float cert_threshold(float a, float b, float c) {
-    return 1e-5f * ((fabsf(a) + fabsf(b)) + fabsf(c));
+    return 8e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
 }
 
 // Octant pieces of the curve of (a, b, c) (c >= 0; not degenerate, not risky)
 // in the frame u = u0 + j*hu (j in [0, nu]), v = v0 + k*hv (k in [0, nv]).
 //
-// The circle is cut at its 45-degree points: the top and bottom quarters
-// (|dv/du| <= 1) are scanned along vertex columns, the left and right
-// quarters (|du/dv| <= 1) along vertex rows.  Each quarter is split at its
+// The circle is cut where its slope in grid-index units is 1 (its 45-degree
+// points on a square grid): the top and bottom quarters (|dv/du| <= hv/hu)
+// are scanned along vertex columns, the left and right quarters
+// (|du/dv| <= hu/hv) along vertex rows, so the crossing moves by at most one
+// index per scanned line.  Each quarter is split at its
 // extreme point into two monotone octants.  Octant p of a quarter:
 //   colp: p = 0 lower root left of the bottom point, 1 lower root right of it,
 //         2 upper root left of the top point, 3 upper root right of it;
@@ -87,7 +93,7 @@ AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, d
         // One straight piece: column mode if |slope| <= 1, else row mode.  Below
         // (left of) the line sigma*F > 0 with sigma = -sign(b) (-sign(a)).
         uint32_t fl = flags;
-        if (fabs(a) <= fabs(b)) {
+        if (fabs(a) * hu <= fabs(b) * hv) {
             s = 0;
             e = nu;
             clip_octant(a, b, 0.0, 0, 0, u0, hu, vlo, vhi, nu, s, e);
@@ -113,14 +119,20 @@ AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, d
     }
     double cu = -a / c, cv = -b / c;
     double r = sqrt(a * a + b * b + c * c) / c;
-    double q = r * 0.70710678118654752440;
+    // Split where the slope in index units is 1: |dv/du| = hv/hu.  With
+    // rho = hv/hu the column band is |u - cu| <= r rho / sqrt(1 + rho^2) and
+    // the row band |v - cv| <= r / sqrt(1 + rho^2) (r / sqrt(2) each on a
+    // square grid).
+    double rho = hv / hu;
+    double qn = 1.0 / sqrt(1.0 + rho * rho);
+    double qu = r * rho * qn, qv = r * qn;
     // Indices are clamped 8 lines outside the frame so that the 3-line
     // extension of a clamped band never reaches into the frame.
     int lim_u = nu + 8, lim_v = nv + 8;
-    int ja = clamp_index(ceil((cu - q - u0) / hu), -8, lim_u);
-    int jb = clamp_index(floor((cu + q - u0) / hu), -8, lim_u);
-    int ka = clamp_index(ceil((cv - q - v0) / hv), -8, lim_v);
-    int kb = clamp_index(floor((cv + q - v0) / hv), -8, lim_v);
+    int ja = clamp_index(ceil((cu - qu - u0) / hu), -8, lim_u);
+    int jb = clamp_index(floor((cu + qu - u0) / hu), -8, lim_u);
+    int ka = clamp_index(ceil((cv - qv - v0) / hv), -8, lim_v);
+    int kb = clamp_index(floor((cv + qv - v0) / hv), -8, lim_v);
     if (jb < ja) jb = ja;
     if (kb < ka) kb = ka;
     int jm = clamp_index(floor((cu - u0) / hu), ja, jb);
@@ -254,63 +266,138 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
     }
 }
 
-// Walk octant cells [cs, ce) of a frame.  The voted cells of cell line j are
-// cross indices min(lo_j, lo_j+1) - 1 .. max(hi_j, hi_j+1), handed to
-// emit(j, klo, khi) (unclipped).
-//
-// Certified step (one evaluation per line): on lines where the octant is
-// monotone with |slope| <= 1 the transition moves by at most one index per
-// line in direction dir.  If line j's bracketing vertices (lo-1 below, lo
-// above) are certified (|sigma*F| > T), then on line j+1 only the vertex in
-// the direction of motion needs evaluating: a certified sign there decides
-// whether the transition moved, and the other bracketing vertex inherits its
-// certificate because its cross distance to the curve can only grow.  Any
-// uncertain value (|sigma*F| <= T, zeros included) falls back to the exact
-// search, which is also used for the first line of the walk.
-template <class Emit>
-AOR_HD __forceinline__ void walk_octant(float aL, float bL, float c, int sel, int dir, int slo, int shi, float T,
-                                        float x0, float hx, float y0, float hy, int cs, int ce, Emit& emit,
-                                        uint32_t& bad) {
-    float sigma = sel ? -1.0f : 1.0f;
+// Walks over octant cells [cs, ce) of a frame.  The voted cells of cell line
+// j are cross indices min(lo_j, lo_j+1) - 1 .. max(hi_j, hi_j+1), handed to
+// emit(j, klo, khi) (unclipped).  Both walks start with an exact search on
+// line cs, seeded by the float64 crossing.
+
+// Seed: first-above index near the crossing of line cs, and the exact state.
+AOR_HD __forceinline__ void walk_start(float sb, float sc, float aL, float bL, float c, int sel, float x0, float hx,
+                                       float y0, float hy, int cs, float xx, float ax, int& lo, int& hi, float& flo,
+                                       float& fhi, uint32_t& bad) {
     double xr = (double)x0 + (double)cs * (double)hx;
     double yr = cross_root(aL, bL, c, xr, sel);
     double gt = floor((yr - (double)y0) / (double)hy);
     int g = clamp_index(gt, -16, 1 << 14);
+    find_transition(sb, sc, xx, ax, y0, hy, g, lo, hi, flo, fhi, bad);
+}
+
+// General walk: an exact search on every line.  Used on the few lines where an
+// octant is not known to be monotone with |slope| <= 1 (the line through its
+// extreme point, the three lines past a 45-degree point).
+template <class Emit>
+AOR_HD __forceinline__ void walk_search(float aL, float bL, float c, int sel, float x0, float hx, float y0, float hy,
+                                        int cs, int ce, Emit& emit, uint32_t& bad) {
+    float sigma = sel ? -1.0f : 1.0f;
+    float sa = sigma * aL, sb = sigma * bL, sc = sigma * c;
+    float x = x0 + (float)cs * hx;
+    float xx = x * x, ax = sa * x;
+    int lo, hi, lo1, hi1;
+    float flo, fhi;
+    walk_start(sb, sc, aL, bL, c, sel, x0, hx, y0, hy, cs, xx, ax, lo, hi, flo, fhi, bad);
+    for (int j = cs; j < ce; ++j) {
+        x += hx;
+        xx = x * x;
+        ax = sa * x;
+        find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo, fhi, bad);
+        emit(j, (lo < lo1 ? lo : lo1) - 1, hi > hi1 ? hi : hi1);
+        lo = lo1;
+        hi = hi1;
+    }
+}
+
+// Certified walk on lines where the octant is monotone (direction dir) with
+// |slope| <= 1, so the crossing moves by at most one line spacing per step.
+//
+// State on line j: lo/hi and two certificates, cb ("vertex lo-1 lies below the
+// curve by a margin") and ca ("vertex hi+1 lies above it by a margin"); a
+// value sigma*F > T (< -T) certifies a vertex.  A certified cross gap carries
+// over to the same index on the next line on the side the curve moves away
+// from, and to the next index on the side it moves towards.  So on line j+1
+// only one or two rows next to the old transition can change side (rows
+// lo .. hi+1 of a rising octant, lo-1 .. hi of a falling one, one more where a
+// certificate is missing); they are evaluated, every other row keeps its
+// certified side.  An evaluated vertex that is not certified is the one
+// nearest the crossing (at most one per line), its neighbours are certain, and
+// its binary32 sign decides the pattern exactly.
+template <class Emit>
+AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel, int dir, float T, float x0, float hx,
+                                           float y0, float hy, int cs, int ce, Emit& emit, uint32_t& bad) {
+    float sigma = sel ? -1.0f : 1.0f;
     float sa = sigma * aL, sb = sigma * bL, sc = sigma * c;
     float x = x0 + (float)cs * hx;
     float xx = x * x, ax = sa * x;
     int lo, hi;
     float flo, fhi;
-    find_transition(sb, sc, xx, ax, y0, hy, g, lo, hi, flo, fhi, bad);
-    bool cert = (hi == lo - 1) && (flo < -T) && (fhi > T);
-    const int off = dir < 0 ? 1 : 0;   // evaluated vertex: lo (rising) or lo - 1 (falling)
+    walk_start(sb, sc, aL, bL, c, sel, x0, hx, y0, hy, cs, xx, ax, lo, hi, flo, fhi, bad);
+    // certificates of the bracketing vertices after the search
+    bool cb = (hi == lo - 1) ? (fhi > T) : true;
+    bool ca = (hi == lo - 1) ? (flo < -T) : true;
+    if (hi >= lo) {
+        // a zero vertex at lo..hi: its neighbours were found non-zero by the
+        // search; certify them by evaluation
+        float yb = y0 + (float)(lo - 1) * hy, ya = y0 + (float)(hi + 1) * hy;
+        cb = vertex_F(sb, sc, xx, ax, yb) > T;
+        ca = vertex_F(sb, sc, xx, ax, ya) < -T;
+    }
+    const int off = dir < 0 ? 1 : 0;
     for (int j = cs; j < ce; ++j) {
         x += hx;
         xx = x * x;
         ax = sa * x;
+        // Rows that may change side on line j+1 (all others keep a certified
+        // side): rising, lo .. hi+1 widened by one below without cb and one
+        // above without ca; falling, lo-1 .. hi widened the same way.
+        const int r0 = lo - off - (cb ? 0 : 1);
+        const int r1 = hi + 1 - off + (ca ? 0 : 1);
+        if (r1 > r0 + 1) bad |= 8u;   // cannot happen: one uncertain vertex per line
+        float y = y0 + (float)r0 * hy;
+        float f0 = vertex_F(sb, sc, xx, ax, y);
+        float f1 = f0;
+        if (r1 > r0) f1 = vertex_F(sb, sc, xx, ax, y + hy);
         int lo1, hi1;
-        bool fast = cert && j >= slo && j + 1 <= shi;
-        float f = 0.0f;
-        if (fast) {
-            float y = y0 + (float)(lo - off) * hy;
-            f = vertex_F(sb, sc, xx, ax, y);
-            fast = (f > T) || (f < -T);
+        if (f0 <= 0.0f) lo1 = r0; else if (r1 > r0 && f1 <= 0.0f) lo1 = r1; else lo1 = r1 + 1;
+        if (r1 > r0 && f1 >= 0.0f) hi1 = r1; else if (f0 >= 0.0f) hi1 = r0; else hi1 = r0 - 1;
+        // certificates on line j+1
+        const int bv = lo1 - 1, av = hi1 + 1;
+        bool cb1 = bv < r0 ? true : ((bv == r0 ? f0 : f1) > T);
+        bool ca1 = av > r1 ? true : ((av == r0 ? f0 : f1) < -T);
+        if ((r1 > r0 && f0 < 0.0f && f1 > 0.0f) || (!cb1 && !ca1) || (bv > r1) || (av < r0)) {
+            // pattern inconsistent with the analysis: exact search instead
+            float flo2, fhi2;
+            find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo2, fhi2, bad);
+            cb1 = false;
+            ca1 = false;
+            if (hi1 == lo1 - 1) {
+                cb1 = fhi2 > T;
+                ca1 = flo2 < -T;
+            }
+            if (!cb1 || !ca1) {
+                // certify the bracketing vertices directly (rare path)
+                float yb = y0 + (float)(lo1 - 1) * hy, ya = y0 + (float)(hi1 + 1) * hy;
+                cb1 = vertex_F(sb, sc, xx, ax, yb) > T;
+                ca1 = vertex_F(sb, sc, xx, ax, ya) < -T;
+                if (!cb1 || !ca1) bad |= 4u;
+            }
         }
-        if (fast) {
-            // rising: below -> lo + 1; falling: above -> lo - 1
-            bool moved = dir > 0 ? (f > T) : (f < -T);
-            lo1 = moved ? lo + dir : lo;
-            hi1 = lo1 - 1;
-        } else {
-            find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo, fhi, bad);
-            cert = (hi1 == lo1 - 1) && (flo < -T) && (fhi > T);
-        }
-        int klo = (lo < lo1 ? lo : lo1) - 1;
-        int khi = hi > hi1 ? hi : hi1;
-        emit(j, klo, khi);
+        emit(j, (lo < lo1 ? lo : lo1) - 1, hi > hi1 ? hi : hi1);
         lo = lo1;
         hi = hi1;
+        cb = cb1;
+        ca = ca1;
     }
+}
+
+// Cells [cs, ce) of octant p split into the certified part and the lines
+// around it that need a search: parts[0..2] = head (search), body
+// (certified), tail (search); empty parts have s >= e.
+AOR_HD __forceinline__ void split_piece(int cs, int ce, int slo, int shi, int2* parts) {
+    int b0 = cs > slo ? cs : slo;
+    int b1 = ce < shi ? ce : shi;
+    if (b1 < b0) b1 = b0;
+    parts[0] = make_int2(cs, b0 < ce ? b0 : ce);
+    parts[1] = make_int2(b0, b1);
+    parts[2] = make_int2(b1 > cs ? b1 : cs, ce);
 }
 
 }  // namespace aoresp

@@ -215,3 +215,31 @@ def test_paper_scale_sampled_parity(aor, orc):
     assert_result_equal(r, fin)
     assert np.array_equal(out["mask"].cpu().numpy(), fin["mask"])
     assert orc.rotation_error_deg(inst.R_gt[0], r["R"]) < 0.5
+
+
+def rot(axis, t):
+    axis = np.asarray(axis, dtype=np.float64) / np.linalg.norm(axis)
+    K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+    return np.eye(3) + math.sin(t) * K + (1 - math.cos(t)) * K @ K
+
+
+@pytest.mark.parametrize("uv", [(0.995, 0.01), (-0.02, -0.997), (0.70, 0.70)])
+def test_refinement_window_at_grid_edge(aor, orc, uv):
+    """Axis projecting next to the border of the grid: the refinement window
+    is clipped to 2 x 3 (or 2 x 2) coarse cells, so its fine cells are not
+    square."""
+    u, v = uv
+    s = u * u + v * v
+    r = np.array([2 * u / (1 + s), 2 * v / (1 + s), (s - 1) / (1 + s)])
+    rng = np.random.default_rng(int(1000 * (u + 2)))
+    n = 1200
+    P = rng.uniform(-1, 1, (3, n)).astype(np.float32)
+    Q = rng.uniform(-1, 1, (3, n)).astype(np.float32)
+    Q[:, :300] = (rot(r, 0.7) @ P[:, :300].astype(np.float64)).astype(np.float32)
+    G, M, B = 128, 32, 720
+    prm = aor.SolveParams(grid=G, refine_grid=M, angle_bins=B)
+    out = aor.solve_debug(dev(P), dev(Q), prm)
+    r_or = orc.solve(P, Q, G=G, B=B, M=M, want_grids=True)
+    assert np.array_equal(out["grid"].cpu().numpy().view(np.uint32), r_or["grid_full"])
+    assert np.array_equal(out["fine"].cpu().numpy().view(np.uint32), r_or["fine"])
+    assert_result_equal(out["result"], r_or)
