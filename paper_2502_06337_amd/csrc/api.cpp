@@ -180,6 +180,7 @@ aoresp_status HostBuf::ensure(size_t need) {
 static constexpr double kVoteTarget = 3.0e6;
 static constexpr int kCellChunk = 65536;
 static constexpr int kCorrChunk = 4096;
+static constexpr int kListChunk = 512;
 
 aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps, const int* npk,
                          Plan& plan) {
@@ -249,6 +250,11 @@ aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const Re
             int64_t i1 = i0 + kCorrChunk < n ? i0 + kCorrChunk : n;
             plan.corr_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
         }
+        if (rp.M > 0)
+            for (int64_t i0 = 0; i0 < n; i0 += kListChunk) {
+                int64_t i1 = i0 + kListChunk < n ? i0 + kListChunk : n;
+                plan.list_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
+            }
     }
     std::stable_sort(votes.begin(), votes.end(),
                      [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
@@ -280,12 +286,17 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
     if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
     if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
+    if (plan.maxM > 0) {
+        if ((st = w.flist.ensure(nn * sizeof(int32_t))) != AORESP_OK) return st;
+        if ((st = w.fcount.ensure((size_t)ninst * sizeof(uint32_t) + 4)) != AORESP_OK) return st;
+    }
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
     const size_t o_vote = (b_inst + 255) / 256 * 256;
     const size_t o_cell = o_vote + plan.vote_items.size() * sizeof(int4);
     const size_t o_corr = o_cell + plan.cell_items.size() * sizeof(int4);
-    const size_t total = o_corr + plan.corr_items.size() * sizeof(int4) + 16;
+    const size_t o_list = o_corr + plan.corr_items.size() * sizeof(int4);
+    const size_t total = o_list + plan.list_items.size() * sizeof(int4) + 16;
     if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
     if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
     char* hb = w.h_plan.as<char>();
@@ -296,12 +307,15 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
         std::memcpy(hb + o_cell, plan.cell_items.data(), plan.cell_items.size() * sizeof(int4));
     if (!plan.corr_items.empty())
         std::memcpy(hb + o_corr, plan.corr_items.data(), plan.corr_items.size() * sizeof(int4));
+    if (!plan.list_items.empty())
+        std::memcpy(hb + o_list, plan.list_items.data(), plan.list_items.size() * sizeof(int4));
     AOR_HIP(hipMemcpyAsync(w.plan.ptr, hb, total, hipMemcpyHostToDevice, s));
     char* db = w.plan.as<char>();
     const Inst* insts = reinterpret_cast<const Inst*>(db);
     const int4* vote_items = reinterpret_cast<const int4*>(db + o_vote);
     const int4* cell_items = reinterpret_cast<const int4*>(db + o_cell);
     const int4* corr_items = reinterpret_cast<const int4*>(db + o_corr);
+    const int4* list_items = reinterpret_cast<const int4*>(db + o_list);
 
     ArcRecs R{w.abc.as<float4>(), w.colp.as<int4>(), w.rowp.as<int4>(), w.geo.as<int4>()};
     PeakState* stt = w.st.as<PeakState>();
@@ -328,9 +342,13 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     mark(3);
     if (plan.maxM > 0) launch_zero_u32(w.fine.as<uint32_t>(), plan.fine_cells, s);
     for (int t = 0; t < plan.max_npk; ++t) {
-        if (plan.maxM > 0)
-            launch_fine_vote(R, insts, corr_items, (int)plan.corr_items.size(), stt, t, w.fine.as<uint32_t>(), err,
-                             plan.maxM, s);
+        if (plan.maxM > 0) {
+            launch_zero_u32(w.fcount.as<uint32_t>(), (size_t)ninst, s);
+            launch_fine_filter(R, insts, corr_items, (int)plan.corr_items.size(), stt, t, w.flist.as<int32_t>(),
+                               w.fcount.as<uint32_t>(), s);
+            launch_fine_vote(R, insts, list_items, (int)plan.list_items.size(), stt, t, w.flist.as<int32_t>(),
+                             w.fcount.as<uint32_t>(), w.fine.as<uint32_t>(), err, plan.maxM, s);
+        }
         launch_fine_peak(w.fine.as<uint32_t>(), insts, ninst, stt, t, s);
     }
     mark(4);
@@ -389,8 +407,8 @@ aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, st
 }
 
 void release_workspace(Workspace& w) {
-    DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys,
-                      &w.st, &w.res, &w.err, &w.plan, &w.P, &w.Q, &w.masks};
+    DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.st,
+                      &w.res, &w.err, &w.flist, &w.fcount, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
     HostBuf* hb[] = {&w.h_plan, &w.h_res, &w.h_st};
     for (HostBuf* b : hb) {

@@ -86,8 +86,9 @@ struct CoarseEmit {
         klo = max(klo, max(dlo, clo));
         khi = min(khi, min(dhi, chi));
         if (mode == 0) {
-            uint32_t* t = tile + jl;
-            for (int k = klo; k <= khi; ++k) atomicAdd(t + k * bw, 1u);
+            // column pass: cell (k, jl) at k*bw + (jl ^ (k & (bw-1))), so lanes on
+            // the same column but different rows hit different LDS banks
+            for (int k = klo; k <= khi; ++k) atomicAdd(tile + k * bw + (jl ^ (k & (bw - 1))), 1u);
         } else {
             uint32_t* t = tile + (size_t)jl * G;
             for (int k = klo; k <= khi; ++k) atomicAdd(t + k, 1u);
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     const float4 abc = R.abc[base0 + b0 + risky[r]];
                     for (int t = tid; t < tile_cells; t += kVoteThreads) {
                         const int k = t / bwb;
-                        const int jl = t - k * bwb;
+                        const int jl = (t - k * bwb) ^ (k & (bwb - 1));
                         if (k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
                         const int j = band0 + jl;
                         float u0 = -1.0f + (float)j * h, u1 = -1.0f + (float)(j + 1) * h;
@@ -242,7 +243,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
             size_t gi;
             if (mode == 0) {
                 int k = t / bwb;
-                gi = (size_t)k * G + band0 + (t - k * bwb);
+                gi = (size_t)k * G + band0 + ((t - k * bwb) ^ (k & (bwb - 1)));
             } else {
                 gi = (size_t)band0 * G + t;
             }
@@ -392,15 +393,84 @@ struct FineEmit {
         for (int k = klo; k <= khi; ++k) {
             int jx = mode == 0 ? j : k, jy = mode == 0 ? k : j;
             if (!all_in && !in_disk(jx, jy)) continue;
-            atomicAdd(&tile[jy * M + jx], 1u);
+            atomicAdd(&tile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
         }
     }
 };
 
-// Fine accumulator of peak `slot`: every correspondence whose curve crosses
-// the window walks it on the M x M fine grid (LDS), then flushes.
+// The refinement window of a peak and the quick-reject geometry.
+struct FineGeom {
+    FineWin fw;
+    bool all_in;   // every fine cell meets the disk
+    double Uc, Vc, Rw, margin;
+};
+
+__device__ __forceinline__ void fine_geom(const FineWin& fw, int M, FineGeom& g) {
+    g.fw = fw;
+    // The window is [U0, U0 + M hx] x [V0, V0 + M hy].  If its corner farthest
+    // from the origin is inside the disk with room to spare, every fine cell
+    // meets the disk and the per-cell test is skipped.
+    double wu = (double)fw.hx * M, wv = (double)fw.hy * M;
+    double ue = fmax(fabs((double)fw.U0), fabs((double)fw.U0 + wu));
+    double ve = fmax(fabs((double)fw.V0), fabs((double)fw.V0 + wv));
+    g.all_in = ue * ue + ve * ve < 1.0 - 1e-4;
+    g.Uc = (double)fw.U0 + 0.5 * wu;
+    g.Vc = (double)fw.V0 + 0.5 * wv;
+    g.Rw = 0.5 * sqrt(wu * wu + wv * wv);
+    g.margin = 2.0 * (double)(fw.hx > fw.hy ? fw.hx : fw.hy);
+}
+
+// Quick reject: over the window |F(x) - F(centre)| <= |grad F(centre)| Rw +
+// |c| Rw^2; if |F| stays above the binary32 error bound everywhere, every
+// vertex has the same sign and no fine cell is voted.
+__device__ __forceinline__ bool fine_may_cross(const float4& abc, uint32_t fl, const FineGeom& g) {
+    if (fl & kFlagDegenerate) return false;
+    if (fl & kFlagRisky) return true;
+    double a = abc.x, b = abc.y, c = abc.z;
+    double Fc = c * (g.Uc * g.Uc + g.Vc * g.Vc - 1.0) + 2.0 * (a * g.Uc + b * g.Vc);
+    double gx = 2.0 * (c * g.Uc + a), gy = 2.0 * (c * g.Vc + b);
+    double bound = sqrt(gx * gx + gy * gy) * g.Rw + fabs(c) * g.Rw * g.Rw;
+    double ebound = 2e-6 * (fabs(a) + fabs(b) + fabs(c));
+    return !(fabs(Fc) > 1.0001 * bound + ebound);
+}
+
+// Pass 1 of the fine vote of peak `slot`: list the correspondences whose
+// curve may cross the refinement window (per instance, at its column offset).
+__global__ __launch_bounds__(256) void k_fine_filter(const ArcRecs R, const Inst* __restrict__ insts,
+                                                     const int4* __restrict__ items, const PeakState* st, int slot,
+                                                     int32_t* __restrict__ list, uint32_t* __restrict__ counts) {
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
+    if (I.M <= 0 || slot >= I.npk) return;
+    const PeakState& s = st[I.res_off + slot];
+    if (!s.valid) return;
+    FineGeom g;
+    fine_geom(s.win, I.M, g);
+    for (int64_t li0 = wi.y; li0 < wi.z; li0 += blockDim.x) {
+        const int64_t li = li0 + threadIdx.x;
+        bool hit = false;
+        if (li < wi.z) {
+            const int64_t gi = I.off + li;
+            hit = fine_may_cross(R.abc[gi], (uint32_t)R.geo[gi].w, g);
+        }
+        unsigned long long bal = __ballot(hit);
+        if (!bal) continue;
+        const int lane = threadIdx.x & 63;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&counts[wi.x], (uint32_t)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (hit) {
+            unsigned long long below = bal & ((1ull << lane) - 1ull);
+            list[I.off + base + (uint32_t)__popcll(below)] = (int32_t)li;
+        }
+    }
+}
+
+// Pass 2: the listed curves walk the M x M fine grid in LDS, then flush.
 __global__ __launch_bounds__(256) void k_fine_vote(const ArcRecs R, const Inst* __restrict__ insts,
                                                    const int4* __restrict__ items, const PeakState* st, int slot,
+                                                   const int32_t* __restrict__ list,
+                                                   const uint32_t* __restrict__ counts,
                                                    uint32_t* __restrict__ fine_arena, uint32_t* __restrict__ err) {
     extern __shared__ __align__(16) uint32_t ftile[];
     const int4 wi = items[blockIdx.x];
@@ -408,42 +478,25 @@ __global__ __launch_bounds__(256) void k_fine_vote(const ArcRecs R, const Inst* 
     if (I.M <= 0 || slot >= I.npk) return;
     const PeakState& s = st[I.res_off + slot];
     if (!s.valid) return;
+    const int64_t cnt = counts[wi.x];
+    if (wi.y >= cnt) return;
+    const int64_t c1 = wi.z < cnt ? wi.z : cnt;
     const int M = I.M;
-    const FineWin fw = s.win;
+    FineGeom g;
+    fine_geom(s.win, M, g);
+    const FineWin& fw = g.fw;
     for (int t = threadIdx.x; t < M * M; t += blockDim.x) ftile[t] = 0u;
     __syncthreads();
-    // The window is [U0, U0 + M hx] x [V0, V0 + M hy].  If its corner farthest
-    // from the origin is inside the disk with room to spare, every fine cell
-    // meets the disk and the per-cell test is skipped.
-    double wu = (double)fw.hx * M, wv = (double)fw.hy * M;
-    double ue = fmax(fabs((double)fw.U0), fabs((double)fw.U0 + wu));
-    double ve = fmax(fabs((double)fw.V0), fabs((double)fw.V0 + wv));
-    bool all_in = ue * ue + ve * ve < 1.0 - 1e-4;
-    double Uc = (double)fw.U0 + 0.5 * wu, Vc = (double)fw.V0 + 0.5 * wv;
-    double Rw = 0.5 * sqrt(wu * wu + wv * wv);
-    double margin = 2.0 * (double)(fw.hx > fw.hy ? fw.hx : fw.hy);
     uint32_t bad = 0;
-    for (int64_t li = wi.y + threadIdx.x; li < wi.z; li += blockDim.x) {
-        const int64_t gi = I.off + li;
+    for (int64_t pos = wi.y + threadIdx.x; pos < c1; pos += blockDim.x) {
+        const int64_t gi = I.off + list[I.off + pos];
         float4 abc = R.abc[gi];
         uint32_t fl = (uint32_t)R.geo[gi].w;
-        if (fl & kFlagDegenerate) continue;
-        double a = abc.x, b = abc.y, c = abc.z;
-        // Quick reject: over the window |F(x) - F(centre)| <= |grad F(centre)| Rw
-        // + |c| Rw^2; if |F| stays above the binary32 error bound everywhere,
-        // every vertex has the same sign and no fine cell is voted.
-        if (!(fl & kFlagRisky)) {
-            double Fc = c * (Uc * Uc + Vc * Vc - 1.0) + 2.0 * (a * Uc + b * Vc);
-            double gx = 2.0 * (c * Uc + a), gy = 2.0 * (c * Vc + b);
-            double bound = sqrt(gx * gx + gy * gy) * Rw + fabs(c) * Rw * Rw;
-            double ebound = 2e-6 * (fabs(a) + fabs(b) + fabs(c));
-            if (fabs(Fc) > 1.0001 * bound + ebound) continue;
-        }
-        FineEmit em{ftile, 0, M, fw.U0, fw.V0, fw.hx, fw.hy, all_in, -(1 << 20), 1 << 20};
+        FineEmit em{ftile, 0, M, fw.U0, fw.V0, fw.hx, fw.hy, g.all_in, -(1 << 20), 1 << 20};
         if (fl & kFlagRisky) {
             for (int jy = 0; jy < M; ++jy)
                 for (int jx = 0; jx < M; ++jx) {
-                    if (!all_in && !em.in_disk(jx, jy)) continue;
+                    if (!g.all_in && !em.in_disk(jx, jy)) continue;
                     float u0 = fw.U0 + (float)jx * fw.hx, u1 = fw.U0 + (float)(jx + 1) * fw.hx;
                     float v0 = fw.V0 + (float)jy * fw.hy, v1 = fw.V0 + (float)(jy + 1) * fw.hy;
                     float uu0 = u0 * u0, uu1 = u1 * u1, au0 = abc.x * u0, au1 = abc.x * u1;
@@ -453,12 +506,12 @@ __global__ __launch_bounds__(256) void k_fine_vote(const ArcRecs R, const Inst* 
                     float f3 = vertex_F(abc.y, abc.z, uu1, au1, v1);
                     bool le = (f0 <= 0.0f) | (f1 <= 0.0f) | (f2 <= 0.0f) | (f3 <= 0.0f);
                     bool ge = (f0 >= 0.0f) | (f1 >= 0.0f) | (f2 >= 0.0f) | (f3 >= 0.0f);
-                    if (le && ge) atomicAdd(&ftile[jy * M + jx], 1u);
+                    if (le && ge) atomicAdd(&ftile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
                 }
             continue;
         }
         int4 colp, rowp, geo;
-        circle_pieces(abc.x, abc.y, abc.z, fl, fw.U0, fw.hx, M, fw.V0, fw.hy, M, margin, colp, rowp, geo);
+        circle_pieces(abc.x, abc.y, abc.z, fl, fw.U0, fw.hx, M, fw.V0, fw.hy, M, g.margin, colp, rowp, geo);
         int32_t cps[4] = {colp.x, colp.y, colp.z, colp.w};
         int32_t rps[4] = {rowp.x, rowp.y, rowp.z, rowp.w};
         int ja, jb;
@@ -494,7 +547,8 @@ __global__ __launch_bounds__(256) void k_fine_vote(const ArcRecs R, const Inst* 
     uint32_t* fine = fine_arena + I.fine_off + (size_t)slot * M * M;
     for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
         uint32_t v = ftile[t];
-        if (v) atomicAdd(&fine[t], v);
+        const int jy = t / M;
+        if (v) atomicAdd(&fine[jy * M + ((t - jy * M) ^ (jy & (M - 1)))], v);
     }
 }
 
@@ -711,14 +765,22 @@ __global__ __launch_bounds__(1024) void k_angle_peak(const uint32_t* __restrict_
 }
 
 // ||R p - q||^2 <= tau^2 per correspondence (Eq. (1)); masks[slot*N + i] if
-// masks is non-null; counts land in res[..].n_inliers.
+// masks is non-null; counts land in res[..].n_inliers (one atomic per block
+// and slot when the block lies in one instance, else one per wave or lane).
 __global__ __launch_bounds__(256) void k_inliers(const float* __restrict__ P, const float* __restrict__ Q,
                                                  int64_t N, const Inst* __restrict__ insts, int ninst,
                                                  const PeakState* st, aoresp_result* res,
                                                  uint8_t* __restrict__ masks) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool live = i < N;
-    int b = live ? find_inst(insts, ninst, i) : 0;
+    __shared__ uint32_t cnt[kMaxPeaks];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t last = min(first + (int64_t)blockDim.x, N) - 1;
+    const int bfirst = find_inst(insts, ninst, first);
+    const bool block_uniform = find_inst(insts, ninst, last) == bfirst;
+    if (threadIdx.x < kMaxPeaks) cnt[threadIdx.x] = 0u;
+    __syncthreads();
+    const bool live = i < N;
+    const int b = live ? (block_uniform ? bfirst : find_inst(insts, ninst, i)) : bfirst;
     const Inst& I = insts[b];
     float p0 = 0, p1 = 0, p2 = 0, q0 = 0, q1 = 0, q2 = 0;
     if (live) {
@@ -730,12 +792,11 @@ __global__ __launch_bounds__(256) void k_inliers(const float* __restrict__ P, co
         q2 = Q[2 * N + i];
     }
     const float tt = I.tau * I.tau;
-    // all live lanes of the wave in one instance: one atomic per wave
-    int b0 = __shfl(b, 0, 64);
-    bool uniform = __all(!live || b == b0);
+    const int npk = insts[bfirst].npk;
     for (int t = 0; t < kMaxPeaks; ++t) {
+        if (block_uniform && t >= npk) break;
         bool act = live && t < I.npk;
-        if (!__any(act)) break;
+        if (!block_uniform && !__any(act)) break;
         uint8_t m = 0;
         if (act && I.n >= 2 && st[I.res_off + t].valid) {
             const float* R = res[I.res_off + t].R;
@@ -755,15 +816,17 @@ __global__ __launch_bounds__(256) void k_inliers(const float* __restrict__ P, co
             m = res2 <= tt ? 1 : 0;
         }
         if (act && masks) masks[(size_t)t * N + i] = m;
-        if (uniform) {
+        if (block_uniform) {
             unsigned long long bal = __ballot(m != 0);
-            if ((threadIdx.x & 63) == 0 && bal) {
-                const Inst& I0 = insts[b0];
-                atomicAdd(&res[I0.res_off + t].n_inliers, (uint32_t)__popcll(bal));
-            }
+            if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&cnt[t], (uint32_t)__popcll(bal));
         } else if (m) {
             atomicAdd(&res[I.res_off + t].n_inliers, 1u);
         }
+    }
+    if (block_uniform) {
+        __syncthreads();
+        if (threadIdx.x < npk && cnt[threadIdx.x])
+            atomicAdd(&res[insts[bfirst].res_off + threadIdx.x].n_inliers, cnt[threadIdx.x]);
     }
 }
 
@@ -825,8 +888,16 @@ void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* 
                        slot);
 }
 
+void launch_fine_filter(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
+                        int32_t* list, uint32_t* counts, hipStream_t s) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(k_fine_filter, dim3((unsigned)nitems), dim3(256), 0, s, recs, insts, items, st, slot, list,
+                       counts);
+}
+
 void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
-                      uint32_t* fine_arena, uint32_t* err, int maxM, hipStream_t s) {
+                      const int32_t* list, const uint32_t* counts, uint32_t* fine_arena, uint32_t* err, int maxM,
+                      hipStream_t s) {
     if (nitems <= 0 || maxM <= 0) return;
     static bool attr = false;
     if (!attr) {
@@ -834,7 +905,7 @@ void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int ni
         attr = true;
     }
     hipLaunchKernelGGL(k_fine_vote, dim3((unsigned)nitems), dim3(256), (size_t)maxM * maxM * 4, s, recs, insts, items,
-                       st, slot, fine_arena, err);
+                       st, slot, list, counts, fine_arena, err);
 }
 
 void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, PeakState* st, int slot,

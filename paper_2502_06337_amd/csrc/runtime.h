@@ -52,6 +52,7 @@ struct Workspace {
     DevBuf abc, colp, rowp, geo;    // per global column
     DevBuf grid, fine, hist;        // arenas
     DevBuf keys, st, res, err;      // per result slot (+ err flag, vote counter)
+    DevBuf flist, fcount;           // fine-vote candidate list (per column) and counts (per instance)
     DevBuf plan;                    // instance table + work items
     DevBuf P, Q, masks;             // staging for host-pointer entry points
     HostBuf h_plan, h_res, h_st;    // pinned mirrors
@@ -61,7 +62,7 @@ struct Workspace {
 // A batch laid out for the kernels.
 struct Plan {
     std::vector<Inst> insts;
-    std::vector<int4> vote_items, cell_items, corr_items;
+    std::vector<int4> vote_items, cell_items, corr_items, list_items;
     int64_t N = 0;
     size_t grid_cells = 0, fine_cells = 0, hist_cells = 0;
     int nres = 0;              // result slots (sum of npk)
