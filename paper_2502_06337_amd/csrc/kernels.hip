@@ -74,25 +74,28 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
 // Coarse accumulator: banded LDS tiles, persistent work-groups
 // --------------------------------------------------------------------------
 
+// Cells of a band tile.  Rows outside the disk are counted here and dropped
+// when the tile is flushed, so the walk only clips to the frame (and, in the
+// row pass, to the columns its quarter owns).
 struct CoarseEmit {
     uint32_t* tile;
-    const int16_t* dlim;   // in-disk limits per cell line of the band (LDS copy)
-    int mode;              // 0: column pass (tile G rows x bw cols), 1: row pass (bw rows x G cols)
-    int band0, bw, G;
-    int clo, chi;          // row pass: allowed columns from the quarter ownership
+    int band0;
+    // Cell (along jl, cross k) sits at (k << ksh) + ((jl << jsh) ^ (k & swz)):
+    // column pass (tile G rows x bw cols) ksh = log2 bw, jsh = 0, swz = bw - 1,
+    // so lanes on one column but different rows hit different LDS banks; row
+    // pass (bw rows x G cols) ksh = 0, jsh = log2 G, swz = 0.
+    int ksh, jsh, swz;
+    int clo, chi;          // allowed cross indices: the frame, and in the row pass the quarter's columns
+    __device__ __forceinline__ void add(int jb, int k) { atomicAdd(tile + ((k << ksh) + (jb ^ (k & swz))), 1u); }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
-        int jl = j - band0;
-        int dlo = dlim[2 * jl], dhi = dlim[2 * jl + 1];
-        klo = max(klo, max(dlo, clo));
-        khi = min(khi, min(dhi, chi));
-        if (mode == 0) {
-            // column pass: cell (k, jl) at k*bw + (jl ^ (k & (bw-1))), so lanes on
-            // the same column but different rows hit different LDS banks
-            for (int k = klo; k <= khi; ++k) atomicAdd(tile + k * bw + (jl ^ (k & (bw - 1))), 1u);
-        } else {
-            uint32_t* t = tile + (size_t)jl * G;
-            for (int k = klo; k <= khi; ++k) atomicAdd(t + k, 1u);
-        }
+        const int jb = (j - band0) << jsh;
+        klo = max(klo, clo);
+        khi = min(khi, chi);
+        // one or two cells per line on a walk; more only next to a zero vertex
+        if (klo <= khi) add(jb, klo);
+        if (klo + 1 <= khi) add(jb, klo + 1);
+#pragma unroll 1
+        for (int k = klo + 2; k <= khi; ++k) add(jb, k);
     }
 };
 
@@ -125,6 +128,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         const int band0 = band * bw;
         const int bwb = (band0 + bw <= G) ? bw : (G - band0);
         const int tile_cells = G * bwb;
+        const int lbw = 31 - __clz(bwb), lg = 31 - __clz(G);   // both powers of two
         const float h = 2.0f / (float)G;
         for (int t = tid; t < tile_cells; t += kVoteThreads) tile[t] = 0u;
         for (int t = tid; t < bwb; t += kVoteThreads) {
@@ -191,11 +195,10 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                 unpack_range(pr, s, e);
                 int dir, slo, shi;
                 octant_walk_info(mode, p, geo, dir, slo, shi);
-                int2 parts[3];
-                split_piece(max(s, band0), min(e, band0 + bwb), slo, shi, parts);
-                const int cs = parts[part].x, ce = parts[part].y;
+                const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
+                const int cs = pp.x, ce = pp.y;
                 const int sel = p >> 1;
-                CoarseEmit em{tile, dlim, mode, band0, bwb, G, 0, G - 1};
+                CoarseEmit em{tile, band0, mode == 0 ? lbw : 0, mode == 0 ? 0 : lg, mode == 0 ? bwb - 1 : 0, 0, G - 1};
                 float aL = abc.x, bL = abc.y;
                 if (mode == 1) {
                     int ja, jb;
@@ -235,18 +238,23 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
             }
             __syncthreads();
         }
-        // flush the band into this instance's accumulator
+        // flush the band's cells that meet the disk into this instance's accumulator
         uint32_t* grid = grid_arena + I.grid_off;
         for (int t = tid; t < tile_cells; t += kVoteThreads) {
             uint32_t v = tile[t];
             if (!v) continue;
+            int jl, k;
             size_t gi;
             if (mode == 0) {
-                int k = t / bwb;
-                gi = (size_t)k * G + band0 + ((t - k * bwb) ^ (k & (bwb - 1)));
+                k = t / bwb;
+                jl = (t - k * bwb) ^ (k & (bwb - 1));
+                gi = (size_t)k * G + band0 + jl;
             } else {
+                jl = t / G;
+                k = t - jl * G;
                 gi = (size_t)band0 * G + t;
             }
+            if (k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
             atomicAdd(&grid[gi], v);
         }
         __syncthreads();
@@ -387,12 +395,13 @@ struct FineEmit {
         float w11 = ((u1 * u1) + (v1 * v1)) - 1.0f;
         return (w00 <= 0.0f) | (w10 <= 0.0f) | (w01 <= 0.0f) | (w11 <= 0.0f);
     }
+    // Cells outside the disk are counted too and dropped at the flush.
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
         klo = max(klo, max(0, clo));
         khi = min(khi, min(M - 1, chi));
+#pragma unroll 1
         for (int k = klo; k <= khi; ++k) {
             int jx = mode == 0 ? j : k, jy = mode == 0 ? k : j;
-            if (!all_in && !in_disk(jx, jy)) continue;
             atomicAdd(&tile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
         }
     }
@@ -545,10 +554,14 @@ __global__ __launch_bounds__(256) void k_fine_vote(const ArcRecs R, const Inst* 
     if (bad) atomicOr(err, bad << 8);
     __syncthreads();
     uint32_t* fine = fine_arena + I.fine_off + (size_t)slot * M * M;
+    FineEmit em{ftile, 0, M, fw.U0, fw.V0, fw.hx, fw.hy, g.all_in, 0, 0};
     for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
         uint32_t v = ftile[t];
+        if (!v) continue;
         const int jy = t / M;
-        if (v) atomicAdd(&fine[jy * M + ((t - jy * M) ^ (jy & (M - 1)))], v);
+        const int jx = (t - jy * M) ^ (jy & (M - 1));
+        if (!g.all_in && !em.in_disk(jx, jy)) continue;
+        atomicAdd(&fine[jy * M + jx], v);
     }
 }
 

@@ -206,6 +206,7 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
     flo = 0.0f;
     fhi = 0.0f;
     if (f > 0.0f) {
+#pragma unroll 1
         do {
             fprev = f;
             ++k;
@@ -218,6 +219,7 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
         fhi = fprev;
         if (!(f < 0.0f)) {
             if (f > 0.0f) bad = 1u;
+#pragma unroll 1
             while (steps++ < kMaxSteps) {
                 y += hy;
                 if (vertex_F(sb, sc, xx, ax, y) != 0.0f) break;
@@ -226,6 +228,7 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
             hi = k;
         }
     } else if (f < 0.0f) {
+#pragma unroll 1
         do {
             fprev = f;
             --k;
@@ -238,6 +241,7 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
         flo = fprev;
         if (!(f > 0.0f)) {
             if (f < 0.0f) bad = 1u;
+#pragma unroll 1
             while (steps++ < kMaxSteps) {
                 y -= hy;
                 if (vertex_F(sb, sc, xx, ax, y) != 0.0f) break;
@@ -248,6 +252,7 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
     } else {
         int kk = k;
         float yy = y;
+#pragma unroll 1
         while (steps++ < kMaxSteps) {
             yy += hy;
             if (vertex_F(sb, sc, xx, ax, yy) != 0.0f) break;
@@ -256,6 +261,7 @@ AOR_HD __forceinline__ void find_transition(float sb, float sc, float xx, float 
         hi = kk;
         kk = k;
         yy = y;
+#pragma unroll 1
         while (steps++ < kMaxSteps) {
             yy -= hy;
             if (vertex_F(sb, sc, xx, ax, yy) != 0.0f) break;
@@ -347,44 +353,50 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         ax = sa * x;
         // Rows that may change side on line j+1 (all others keep a certified
         // side): rising, lo .. hi+1 widened by one below without cb and one
-        // above without ca; falling, lo-1 .. hi widened the same way.
+        // above without ca; falling, lo-1 .. hi widened the same way.  With
+        // both certificates and no zero vertex this is the single row r0.
         const int r0 = lo - off - (cb ? 0 : 1);
         const int r1 = hi + 1 - off + (ca ? 0 : 1);
-        if (r1 > r0 + 1) bad |= 8u;   // cannot happen: one uncertain vertex per line
-        float y = y0 + (float)r0 * hy;
-        float f0 = vertex_F(sb, sc, xx, ax, y);
-        float f1 = f0;
-        if (r1 > r0) f1 = vertex_F(sb, sc, xx, ax, y + hy);
-        int lo1, hi1;
-        if (f0 <= 0.0f) lo1 = r0; else if (r1 > r0 && f1 <= 0.0f) lo1 = r1; else lo1 = r1 + 1;
-        if (r1 > r0 && f1 >= 0.0f) hi1 = r1; else if (f0 >= 0.0f) hi1 = r0; else hi1 = r0 - 1;
-        // certificates on line j+1
-        const int bv = lo1 - 1, av = hi1 + 1;
-        bool cb1 = bv < r0 ? true : ((bv == r0 ? f0 : f1) > T);
-        bool ca1 = av > r1 ? true : ((av == r0 ? f0 : f1) < -T);
-        if ((r1 > r0 && f0 < 0.0f && f1 > 0.0f) || (!cb1 && !ca1) || (bv > r1) || (av < r0)) {
-            // pattern inconsistent with the analysis: exact search instead
-            float flo2, fhi2;
-            find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo2, fhi2, bad);
-            cb1 = false;
-            ca1 = false;
-            if (hi1 == lo1 - 1) {
-                cb1 = fhi2 > T;
-                ca1 = flo2 < -T;
+        const float y = y0 + (float)r0 * hy;
+        const float f0 = vertex_F(sb, sc, xx, ax, y);
+        // Usual case: one row, certified either way (|f0| > T), so the
+        // transition is r0 or r0 + 1 and both certificates carry over.
+        int lo1 = f0 > 0.0f ? r0 + 1 : r0;
+        int hi1 = lo1 - 1;
+        if (r1 > r0 || !(fabsf(f0) > T)) {
+            if (r1 > r0 + 1) bad |= 8u;   // cannot happen: one uncertain vertex per line
+            float f1 = f0;
+            if (r1 > r0) f1 = vertex_F(sb, sc, xx, ax, y + hy);
+            if (f0 <= 0.0f) lo1 = r0; else if (r1 > r0 && f1 <= 0.0f) lo1 = r1; else lo1 = r1 + 1;
+            if (r1 > r0 && f1 >= 0.0f) hi1 = r1; else if (f0 >= 0.0f) hi1 = r0; else hi1 = r0 - 1;
+            // certificates on line j+1
+            const int bv = lo1 - 1, av = hi1 + 1;
+            bool cb1 = bv < r0 ? true : ((bv == r0 ? f0 : f1) > T);
+            bool ca1 = av > r1 ? true : ((av == r0 ? f0 : f1) < -T);
+            if ((r1 > r0 && f0 < 0.0f && f1 > 0.0f) || (!cb1 && !ca1) || (bv > r1) || (av < r0)) {
+                // pattern inconsistent with the analysis: exact search instead
+                float flo2, fhi2;
+                find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo2, fhi2, bad);
+                cb1 = false;
+                ca1 = false;
+                if (hi1 == lo1 - 1) {
+                    cb1 = fhi2 > T;
+                    ca1 = flo2 < -T;
+                }
+                if (!cb1 || !ca1) {
+                    // certify the bracketing vertices directly (rare path)
+                    float yb = y0 + (float)(lo1 - 1) * hy, ya = y0 + (float)(hi1 + 1) * hy;
+                    cb1 = vertex_F(sb, sc, xx, ax, yb) > T;
+                    ca1 = vertex_F(sb, sc, xx, ax, ya) < -T;
+                    if (!cb1 || !ca1) bad |= 4u;
+                }
             }
-            if (!cb1 || !ca1) {
-                // certify the bracketing vertices directly (rare path)
-                float yb = y0 + (float)(lo1 - 1) * hy, ya = y0 + (float)(hi1 + 1) * hy;
-                cb1 = vertex_F(sb, sc, xx, ax, yb) > T;
-                ca1 = vertex_F(sb, sc, xx, ax, ya) < -T;
-                if (!cb1 || !ca1) bad |= 4u;
-            }
+            cb = cb1;
+            ca = ca1;
         }
         emit(j, (lo < lo1 ? lo : lo1) - 1, hi > hi1 ? hi : hi1);
         lo = lo1;
         hi = hi1;
-        cb = cb1;
-        ca = ca1;
     }
 }
 
@@ -398,6 +410,16 @@ AOR_HD __forceinline__ void split_piece(int cs, int ce, int slo, int shi, int2* 
     parts[0] = make_int2(cs, b0 < ce ? b0 : ce);
     parts[1] = make_int2(b0, b1);
     parts[2] = make_int2(b1 > cs ? b1 : cs, ce);
+}
+
+// Part q of split_piece alone (selects only, so nothing goes to scratch).
+AOR_HD __forceinline__ int2 piece_part(int cs, int ce, int slo, int shi, int q) {
+    int b0 = cs > slo ? cs : slo;
+    int b1 = ce < shi ? ce : shi;
+    if (b1 < b0) b1 = b0;
+    int s = q == 0 ? cs : (q == 1 ? b0 : (b1 > cs ? b1 : cs));
+    int e = q == 0 ? (b0 < ce ? b0 : ce) : (q == 1 ? b1 : ce);
+    return make_int2(s, e);
 }
 
 }  // namespace aoresp
