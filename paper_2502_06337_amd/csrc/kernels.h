@@ -21,7 +21,8 @@ constexpr uint32_t kFlagLineDown = 8u;    // line whose cross coordinate decreas
 constexpr int kMaxPeaks = 8;
 constexpr int kTileCells = 32768;         // u32 cells of one coarse LDS band (128 KiB)
 constexpr int kVoteThreads = 1024;
-constexpr int kQueueCap = 12 * kVoteThreads;   // up to 4 octants x 3 parts per correspondence
+constexpr int kRingBody = 128;     // per-wave ring of certified parts: < 64 left over + <= 64 appended
+constexpr int kRingLine = 256;     // per-wave ring of searched parts: < 64 left over + <= 128 appended
 
 // Per-correspondence records (SoA, one entry per global column).
 //  abc : displacement (a, b, c) negated if needed so that c >= 0; .w = the

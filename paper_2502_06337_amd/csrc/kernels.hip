@@ -99,19 +99,28 @@ struct CoarseEmit {
     }
 };
 
+// One work-group per item (instance, pass, band, correspondence range).  The
+// band tile is zeroed, then every wave works on its own: it takes groups of
+// 64 correspondences, appends the parts of each octant that fall in the band
+// to two per-wave rings in LDS (certified bodies, searched lines), and walks
+// 64 parts at a time whenever a ring holds a full round, so there is no
+// block-wide barrier between listing and walking.  At the end the rings are
+// drained, and the tile is flushed (disk mask applied) with global atomics.
 __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const Inst* __restrict__ insts,
                                                        const int4* __restrict__ items, int nitems,
                                                        uint32_t* __restrict__ counter,
                                                        uint32_t* __restrict__ grid_arena,
                                                        uint32_t* __restrict__ err) {
+    constexpr int kWaves = kVoteThreads / 64;
     extern __shared__ __align__(16) uint32_t smem[];
-    __shared__ uint32_t qcount, wcount, rcount;
     __shared__ int item_id;
     const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
     uint32_t* tile = smem;
-    uint16_t* queue = reinterpret_cast<uint16_t*>(smem + kTileCells);
-    uint16_t* risky = queue + kQueueCap;
-    int16_t* dlim = reinterpret_cast<int16_t*>(risky + kVoteThreads);   // 2 per band line
+    uint32_t* rbody = smem + kTileCells + wid * (kRingBody + kRingLine);
+    uint32_t* rline = rbody + kRingBody;
+    int16_t* dlim = reinterpret_cast<int16_t*>(smem + kTileCells + kWaves * (kRingBody + kRingLine));
+    const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t bad = 0;
 
     for (;;) {
@@ -135,91 +144,88 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
             dlim[2 * t] = I.disk[2 * (band0 + t)];
             dlim[2 * t + 1] = I.disk[2 * (band0 + t) + 1];
         }
-        const int64_t base0 = I.off;
-        for (int64_t b0 = wi.z; b0 < wi.w; b0 += kVoteThreads) {
-            if (tid == 0) {
-                qcount = 0u;
-                wcount = 0u;
-                rcount = 0u;
-            }
-            __syncthreads();
-            int64_t li = b0 + tid;
-            if (li < wi.w) {
-                const int64_t gi = base0 + li;
-                int4 pc = mode == 0 ? R.colp[gi] : R.rowp[gi];
-                if (pc.x == kRiskyMark) {
-                    if (mode == 0) risky[atomicAdd(&rcount, 1u)] = (uint16_t)tid;
+        __syncthreads();
+        const int64_t base = I.off + wi.z;   // entries hold li - wi.z
+        const int64_t nli = (int64_t)wi.w - wi.z;
+        const int4* __restrict__ prange = mode == 0 ? R.colp : R.rowp;
+
+        // wave state (uniform): ring heads and fills, next group, octant step
+        int bh = 0, bn = 0, lh = 0, ln = 0;
+        int64_t g0 = (int64_t)wid * 64;
+        int step = 4;
+        bool draining = false;
+        int64_t li = 0;
+        int4 pc = make_int4(0, 0, 0, 0), geo = pc;
+        int4 pc_next = pc;
+        if (g0 + lane < nli) pc_next = prange[base + g0 + lane];
+        for (;;) {
+            const bool take_b = bn >= 64 || (draining && bn > 0);
+            const bool take_l = !take_b && (ln >= 64 || (draining && ln > 0));
+            if (take_b || take_l) {
+                // one round: lane k walks the k-th oldest part of the chosen ring
+                const int cnt = take_b ? min(bn, 64) : min(ln, 64);
+                if (lane < cnt) {
+                    const uint32_t ent = take_b ? rbody[(bh + lane) & (kRingBody - 1)]
+                                                : rline[(lh + lane) & (kRingLine - 1)];
+                    const int64_t gi = base + (ent >> 4);
+                    const int p = (ent >> 2) & 3;
+                    const int part = ent & 3;
+                    const float4 abc = R.abc[gi];
+                    const int4 pc2 = prange[gi];
+                    const int4 geo2 = R.geo[gi];
+                    const int32_t pr = p == 0 ? pc2.x : (p == 1 ? pc2.y : (p == 2 ? pc2.z : pc2.w));
+                    int s, e;
+                    unpack_range(pr, s, e);
+                    int dir, slo, shi;
+                    octant_walk_info(mode, p, geo2, dir, slo, shi);
+                    const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
+                    const int sel = p >> 1;
+                    CoarseEmit em{tile, band0, mode == 0 ? lbw : 0, mode == 0 ? 0 : lg, mode == 0 ? bwb - 1 : 0,
+                                  0, G - 1};
+                    float aL = abc.x, bL = abc.y;
+                    if (mode == 1) {
+                        int ja, jb;
+                        unpack_range(geo2.x, ja, jb);
+                        if (sel == 0) em.chi = min(G - 1, ja - 1); else em.clo = max(0, jb);
+                        aL = abc.y;
+                        bL = abc.x;
+                    }
+                    if (take_b)
+                        walk_certified(aL, bL, abc.z, sel, dir, abc.w, -1.0f, h, -1.0f, h, pp.x, pp.y, em, bad);
+                    else
+                        walk_search(aL, bL, abc.z, sel, -1.0f, h, -1.0f, h, pp.x, pp.y, em, bad);
+                }
+                if (take_b) {
+                    bh += cnt;
+                    bn -= cnt;
                 } else {
-                    int32_t pcs[4] = {pc.x, pc.y, pc.z, pc.w};
-                    bool any = false;
-#pragma unroll
-                    for (int p = 0; p < 4; ++p) {
-                        int s, e;
-                        unpack_range(pcs[p], s, e);
-                        any |= max(s, band0) < min(e, band0 + bwb);
-                    }
-                    if (any) {
-                        const int4 geo = R.geo[gi];
-#pragma unroll
-                        for (int p = 0; p < 4; ++p) {
-                            int s, e;
-                            unpack_range(pcs[p], s, e);
-                            int cs = max(s, band0);
-                            int ce = min(e, band0 + bwb);
-                            if (cs >= ce) continue;
-                            int dir, slo, shi;
-                            octant_walk_info(mode, p, geo, dir, slo, shi);
-                            int2 parts[3];
-                            split_piece(cs, ce, slo, shi, parts);
-                            // certified bodies from the front, searched lines from the back
-                            if (parts[1].x < parts[1].y) queue[atomicAdd(&qcount, 1u)] = (uint16_t)((tid << 4) | (p << 2) | 1);
-                            if (parts[0].x < parts[0].y) queue[kQueueCap - 1 - atomicAdd(&wcount, 1u)] = (uint16_t)((tid << 4) | (p << 2) | 0);
-                            if (parts[2].x < parts[2].y) queue[kQueueCap - 1 - atomicAdd(&wcount, 1u)] = (uint16_t)((tid << 4) | (p << 2) | 2);
-                        }
-                    }
+                    lh += cnt;
+                    ln -= cnt;
                 }
+                continue;
             }
-            __syncthreads();
-            const int qn = (int)qcount;
-            const int wn = (int)wcount;
-            for (int t = tid; t < qn + wn; t += kVoteThreads) {
-                const int ent = t < qn ? queue[t] : queue[kQueueCap - 1 - (t - qn)];
-                const int64_t gi = base0 + b0 + (ent >> 4);
-                const int p = (ent >> 2) & 3;
-                const int part = ent & 3;
-                const float4 abc = R.abc[gi];
-                const int4 pc = mode == 0 ? R.colp[gi] : R.rowp[gi];
-                const int4 geo = R.geo[gi];
-                const int32_t pr = p == 0 ? pc.x : (p == 1 ? pc.y : (p == 2 ? pc.z : pc.w));
-                int s, e;
-                unpack_range(pr, s, e);
-                int dir, slo, shi;
-                octant_walk_info(mode, p, geo, dir, slo, shi);
-                const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
-                const int cs = pp.x, ce = pp.y;
-                const int sel = p >> 1;
-                CoarseEmit em{tile, band0, mode == 0 ? lbw : 0, mode == 0 ? 0 : lg, mode == 0 ? bwb - 1 : 0, 0, G - 1};
-                float aL = abc.x, bL = abc.y;
-                if (mode == 1) {
-                    int ja, jb;
-                    unpack_range(geo.x, ja, jb);
-                    if (sel == 0) em.chi = min(G - 1, ja - 1); else em.clo = max(0, jb);
-                    aL = abc.y;
-                    bL = abc.x;
+            if (draining) break;
+            if (step == 4) {
+                // next group of 64 correspondences
+                if (g0 >= nli) {
+                    draining = true;
+                    continue;
                 }
-                if (part == 1)
-                    walk_certified(aL, bL, abc.z, sel, dir, abc.w, -1.0f, h, -1.0f, h, cs, ce, em, bad);
-                else
-                    walk_search(aL, bL, abc.z, sel, -1.0f, h, -1.0f, h, cs, ce, em, bad);
-            }
-            if (mode == 0) {
-                // exhaustive cell test for correspondences outside the walk's range of validity
-                const int rn = (int)rcount;
-                for (int r = 0; r < rn; ++r) {
-                    const float4 abc = R.abc[base0 + b0 + risky[r]];
-                    for (int t = tid; t < tile_cells; t += kVoteThreads) {
-                        const int k = t / bwb;
-                        const int jl = (t - k * bwb) ^ (k & (bwb - 1));
+                li = g0 + lane;
+                pc = pc_next;
+                const bool live = li < nli;
+                g0 += kWaves * 64;
+                if (g0 + lane < nli) pc_next = prange[base + g0 + lane];
+                // correspondences outside the walk's range of validity (column
+                // pass only): exhaustive cell test of the band by the whole wave
+                unsigned long long rk = __ballot(live && pc.x == kRiskyMark);
+                while (rk) {
+                    const int l = __ffsll((long long)rk) - 1;
+                    rk &= rk - 1ull;
+                    const float4 abc = R.abc[base + li - lane + l];
+                    for (int t = lane; t < tile_cells; t += 64) {
+                        const int k = t >> lbw;
+                        const int jl = (t - (k << lbw)) ^ (k & (bwb - 1));
                         if (k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
                         const int j = band0 + jl;
                         float u0 = -1.0f + (float)j * h, u1 = -1.0f + (float)(j + 1) * h;
@@ -235,9 +241,52 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                         if (le && ge) atomicAdd(&tile[t], 1u);
                     }
                 }
+                bool any = false;
+                if (live && pc.x != kRiskyMark) {
+#pragma unroll
+                    for (int p = 0; p < 4; ++p) {
+                        const int32_t pr = p == 0 ? pc.x : (p == 1 ? pc.y : (p == 2 ? pc.z : pc.w));
+                        int s, e;
+                        unpack_range(pr, s, e);
+                        any |= max(s, band0) < min(e, band0 + bwb);
+                    }
+                }
+                if (any) geo = R.geo[base + li];
+                step = __ballot(any) ? 0 : 4;
+                if (!any) li = nli;   // nothing of this one in the band
+                continue;
             }
-            __syncthreads();
+            // append the parts of octant `step` that fall in the band
+            {
+                const int p = step;
+                bool hb = false, h0 = false, h2 = false;
+                if (li < nli) {
+                    const int32_t pr = p == 0 ? pc.x : (p == 1 ? pc.y : (p == 2 ? pc.z : pc.w));
+                    int s, e;
+                    unpack_range(pr, s, e);
+                    const int cs = max(s, band0), ce = min(e, band0 + bwb);
+                    if (cs < ce) {
+                        int dir, slo, shi;
+                        octant_walk_info(mode, p, geo, dir, slo, shi);
+                        int2 parts[3];
+                        split_piece(cs, ce, slo, shi, parts);
+                        hb = parts[1].x < parts[1].y;
+                        h0 = parts[0].x < parts[0].y;
+                        h2 = parts[2].x < parts[2].y;
+                    }
+                }
+                const uint32_t key = ((uint32_t)li << 4) | ((uint32_t)p << 2);
+                const unsigned long long mb = __ballot(hb), m0 = __ballot(h0), m2 = __ballot(h2);
+                if (hb) rbody[(bh + bn + __popcll(mb & below)) & (kRingBody - 1)] = key | 1u;
+                const int n0 = __popcll(m0);
+                if (h0) rline[(lh + ln + __popcll(m0 & below)) & (kRingLine - 1)] = key | 0u;
+                if (h2) rline[(lh + ln + n0 + __popcll(m2 & below)) & (kRingLine - 1)] = key | 2u;
+                bn += __popcll(mb);
+                ln += n0 + __popcll(m2);
+                ++step;
+            }
         }
+        __syncthreads();
         // flush the band's cells that meet the disk into this instance's accumulator
         uint32_t* grid = grid_arena + I.grid_off;
         for (int t = tid; t < tile_cells; t += kVoteThreads) {
@@ -246,12 +295,12 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
             int jl, k;
             size_t gi;
             if (mode == 0) {
-                k = t / bwb;
-                jl = (t - k * bwb) ^ (k & (bwb - 1));
+                k = t >> lbw;
+                jl = (t - (k << lbw)) ^ (k & (bwb - 1));
                 gi = (size_t)k * G + band0 + jl;
             } else {
-                jl = t / G;
-                k = t - jl * G;
+                jl = t >> lg;
+                k = t - (jl << lg);
                 gi = (size_t)band0 * G + t;
             }
             if (k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
@@ -853,8 +902,8 @@ __global__ void k_zero_u32(uint32_t* p, size_t count) {
 // --------------------------------------------------------------------------
 
 size_t coarse_lds_bytes() {
-    // tile + queue (u16) + risky list (u16) + in-disk limits (2 x int16 per band line, <= 256 lines)
-    return (size_t)kTileCells * 4 + kQueueCap * 2 + kVoteThreads * 2 + 2 * 2 * 256;
+    // tile + per-wave rings (u32) + in-disk limits (2 x int16 per band line, <= 256 lines)
+    return (size_t)kTileCells * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 2 * 2 * 256;
 }
 
 static void set_lds_limit(const void* fn) {
