@@ -74,28 +74,34 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
 // Coarse accumulator: banded LDS tiles, persistent work-groups
 // --------------------------------------------------------------------------
 
-// Cells of a band tile.  Rows outside the disk are counted here and dropped
-// when the tile is flushed, so the walk only clips to the frame (and, in the
-// row pass, to the columns its quarter owns).
+// Cells of a band tile, stored along-line major: cell (along jl, cross k) at
+// jl * S + k with S = G + 1, so the lanes of a wave (different curves, mostly
+// on the same line) hit spread-out banks, and the column pass's flush, which
+// reads across lines, is conflict-free too.  Cells outside the disk are
+// counted here and dropped at the flush, so the walk only clips to the frame
+// (and, in the row pass, to the columns its quarter owns).
 struct CoarseEmit {
     uint32_t* tile;
-    int band0;
-    // Cell (along jl, cross k) sits at (k << ksh) + ((jl << jsh) ^ (k & swz)):
-    // column pass (tile G rows x bw cols) ksh = log2 bw, jsh = 0, swz = bw - 1,
-    // so lanes on one column but different rows hit different LDS banks; row
-    // pass (bw rows x G cols) ksh = 0, jsh = log2 G, swz = 0.
-    int ksh, jsh, swz;
-    int clo, chi;          // allowed cross indices: the frame, and in the row pass the quarter's columns
-    __device__ __forceinline__ void add(int jb, int k) { atomicAdd(tile + ((k << ksh) + (jb ^ (k & swz))), 1u); }
+    int band0, lg;         // S = 2^lg + 1
+    int clo, chi;          // allowed cross indices
+    __device__ __forceinline__ uint32_t* line_of(int j) const {
+        const int jl = j - band0;
+        return tile + ((jl << lg) + jl);
+    }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
-        const int jb = (j - band0) << jsh;
+        uint32_t* line = line_of(j);
         klo = max(klo, clo);
         khi = min(khi, chi);
-        // one or two cells per line on a walk; more only next to a zero vertex
-        if (klo <= khi) add(jb, klo);
-        if (klo + 1 <= khi) add(jb, klo + 1);
 #pragma unroll 1
-        for (int k = klo + 2; k <= khi; ++k) add(jb, k);
+        for (int k = klo; k <= khi; ++k) atomicAdd(line + k, 1u);
+    }
+    // cell k0, and k1 if use1 (the common case of a walk: one or two cells)
+    __device__ __forceinline__ void two(int j, int k0, int k1, bool use1) {
+        if (chi < clo) return;   // the quarter owns no column here
+        uint32_t* line = line_of(j);
+        const unsigned span = (unsigned)(chi - clo);
+        if ((unsigned)(k0 - clo) <= span) atomicAdd(line + k0, 1u);
+        if (use1 && (unsigned)(k1 - clo) <= span) atomicAdd(line + k1, 1u);
     }
 };
 
@@ -114,17 +120,21 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
     constexpr int kWaves = kVoteThreads / 64;
     extern __shared__ __align__(16) uint32_t smem[];
     __shared__ int item_id;
+    __shared__ int group_next;   // next unclaimed group of 64 correspondences
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     uint32_t* tile = smem;
-    uint32_t* rbody = smem + kTileCells + wid * (kRingBody + kRingLine);
+    uint32_t* rbody = smem + kTileCells + 128 + wid * (kRingBody + kRingLine);
     uint32_t* rline = rbody + kRingBody;
-    int16_t* dlim = reinterpret_cast<int16_t*>(smem + kTileCells + kWaves * (kRingBody + kRingLine));
+    int16_t* dlim = reinterpret_cast<int16_t*>(smem + kTileCells + 128 + kWaves * (kRingBody + kRingLine));
     const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t bad = 0;
 
     for (;;) {
-        if (tid == 0) item_id = (int)atomicAdd(counter, 1u);
+        if (tid == 0) {
+            item_id = (int)atomicAdd(counter, 1u);
+            group_next = kWaves * 64;
+        }
         __syncthreads();
         const int it = item_id;
         if (it >= nitems) break;
@@ -136,7 +146,8 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         const int bw = coarse_band_width(G);
         const int band0 = band * bw;
         const int bwb = (band0 + bw <= G) ? bw : (G - band0);
-        const int tile_cells = G * bwb;
+        const int S = G + 1;                 // tile line stride
+        const int tile_cells = bwb * S;
         const int lbw = 31 - __clz(bwb), lg = 31 - __clz(G);   // both powers of two
         const float h = 2.0f / (float)G;
         for (int t = tid; t < tile_cells; t += kVoteThreads) tile[t] = 0u;
@@ -149,7 +160,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         const int64_t nli = (int64_t)wi.w - wi.z;
         const int4* __restrict__ prange = mode == 0 ? R.colp : R.rowp;
 
-        // wave state (uniform): ring heads and fills, next group, octant step
+        // wave state (uniform): ring heads and fills, next group, octant step.
+        // The first group of each wave is fixed, later ones are claimed from
+        // the block's counter, so waves with lighter groups take more.
         int bh = 0, bn = 0, lh = 0, ln = 0;
         int64_t g0 = (int64_t)wid * 64;
         int step = 4;
@@ -180,8 +193,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     octant_walk_info(mode, p, geo2, dir, slo, shi);
                     const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
                     const int sel = p >> 1;
-                    CoarseEmit em{tile, band0, mode == 0 ? lbw : 0, mode == 0 ? 0 : lg, mode == 0 ? bwb - 1 : 0,
-                                  0, G - 1};
+                    CoarseEmit em{tile, band0, lg, 0, G - 1};
                     float aL = abc.x, bL = abc.y;
                     if (mode == 1) {
                         int ja, jb;
@@ -214,7 +226,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                 li = g0 + lane;
                 pc = pc_next;
                 const bool live = li < nli;
-                g0 += kWaves * 64;
+                int gn = 0;
+                if (lane == 0) gn = atomicAdd(&group_next, 64);
+                g0 = __shfl(gn, 0, 64);
                 if (g0 + lane < nli) pc_next = prange[base + g0 + lane];
                 // correspondences outside the walk's range of validity (column
                 // pass only): exhaustive cell test of the band by the whole wave
@@ -223,9 +237,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     const int l = __ffsll((long long)rk) - 1;
                     rk &= rk - 1ull;
                     const float4 abc = R.abc[base + li - lane + l];
-                    for (int t = lane; t < tile_cells; t += 64) {
+                    for (int t = lane; t < bwb * G; t += 64) {
                         const int k = t >> lbw;
-                        const int jl = (t - (k << lbw)) ^ (k & (bwb - 1));
+                        const int jl = t & (bwb - 1);
                         if (k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
                         const int j = band0 + jl;
                         float u0 = -1.0f + (float)j * h, u1 = -1.0f + (float)(j + 1) * h;
@@ -238,7 +252,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                         float f3 = vertex_F(abc.y, abc.z, uu1, au1, v1);
                         bool le = (f0 <= 0.0f) | (f1 <= 0.0f) | (f2 <= 0.0f) | (f3 <= 0.0f);
                         bool ge = (f0 >= 0.0f) | (f1 >= 0.0f) | (f2 >= 0.0f) | (f3 >= 0.0f);
-                        if (le && ge) atomicAdd(&tile[t], 1u);
+                        if (le && ge) atomicAdd(&tile[jl * S + k], 1u);
                     }
                 }
                 bool any = false;
@@ -287,23 +301,23 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
             }
         }
         __syncthreads();
-        // flush the band's cells that meet the disk into this instance's accumulator
+        // flush the band's cells that meet the disk into this instance's
+        // accumulator; consecutive threads take consecutive grid cells
         uint32_t* grid = grid_arena + I.grid_off;
-        for (int t = tid; t < tile_cells; t += kVoteThreads) {
-            uint32_t v = tile[t];
-            if (!v) continue;
+        for (int t = tid; t < bwb * G; t += kVoteThreads) {
             int jl, k;
             size_t gi;
             if (mode == 0) {
                 k = t >> lbw;
-                jl = (t - (k << lbw)) ^ (k & (bwb - 1));
+                jl = t & (bwb - 1);
                 gi = (size_t)k * G + band0 + jl;
             } else {
                 jl = t >> lg;
-                k = t - (jl << lg);
-                gi = (size_t)band0 * G + t;
+                k = t & (G - 1);
+                gi = (size_t)(band0 + jl) * G + k;
             }
-            if (k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
+            const uint32_t v = tile[jl * S + k];
+            if (!v || k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
             atomicAdd(&grid[gi], v);
         }
         __syncthreads();
@@ -453,6 +467,10 @@ struct FineEmit {
             int jx = mode == 0 ? j : k, jy = mode == 0 ? k : j;
             atomicAdd(&tile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
         }
+    }
+    __device__ __forceinline__ void two(int j, int k0, int k1, bool use1) {
+        (*this)(j, k0, k0);
+        if (use1) (*this)(j, k1, k1);
     }
 };
 
@@ -902,8 +920,9 @@ __global__ void k_zero_u32(uint32_t* p, size_t count) {
 // --------------------------------------------------------------------------
 
 size_t coarse_lds_bytes() {
-    // tile + per-wave rings (u32) + in-disk limits (2 x int16 per band line, <= 256 lines)
-    return (size_t)kTileCells * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 2 * 2 * 256;
+    // tile (bw lines of G + 1 cells, bw <= 128 beyond kTileCells) + per-wave
+    // rings (u32) + in-disk limits (2 x int16 per band line, <= 256 lines)
+    return (size_t)(kTileCells + 128) * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 2 * 2 * 256;
 }
 
 static void set_lds_limit(const void* fn) {

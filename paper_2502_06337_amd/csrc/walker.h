@@ -326,6 +326,15 @@ AOR_HD __forceinline__ void walk_search(float aL, float bL, float c, int sel, fl
 // certified side.  An evaluated vertex that is not certified is the one
 // nearest the crossing (at most one per line), its neighbours are certain, and
 // its binary32 sign decides the pattern exactly.
+//
+// Clean state (both certificates, no zero vertex, hi = lo - 1): the only row
+// to evaluate is r = lo - off (off = 1 on a falling octant), the transition
+// moves to r + (F > 0), and the voted cells of the column are r - 1 + off and,
+// if (F > 0) != off, also r - off.  Such a line costs one vertex evaluation
+// and goes to emit.two(j, first, second, second_voted).  A value |F| <= T
+// leaves one certificate missing; the next line and any zero vertex go through
+// the general step, which evaluates one or two rows and emits the range
+// min(lo) - 1 .. max(hi) of the two lines.
 template <class Emit>
 AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel, int dir, float T, float x0, float hx,
                                            float y0, float hy, int cs, int ce, Emit& emit, uint32_t& bad) {
@@ -347,56 +356,78 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         ca = vertex_F(sb, sc, xx, ax, ya) < -T;
     }
     const int off = dir < 0 ? 1 : 0;
+    bool clean = cb && ca && hi == lo - 1;
+    int r = lo - off;   // the row evaluated next while clean
     for (int j = cs; j < ce; ++j) {
         x += hx;
         xx = x * x;
         ax = sa * x;
-        // Rows that may change side on line j+1 (all others keep a certified
-        // side): rising, lo .. hi+1 widened by one below without cb and one
-        // above without ca; falling, lo-1 .. hi widened the same way.  With
-        // both certificates and no zero vertex this is the single row r0.
+        float f = 0.0f;
+        if (clean) f = vertex_F(sb, sc, xx, ax, y0 + (float)r * hy);
+        if (clean && f != 0.0f) {
+            const int step = f > 0.0f ? 1 : 0;
+            emit.two(j, r - 1 + off, r - off, step != off);
+            r += step - off;
+            if (!(fabsf(f) > T)) {
+                // the evaluated vertex is not certified: leave the clean state
+                clean = false;
+                lo = r + off;
+                hi = lo - 1;
+                cb = !(f > 0.0f);
+                ca = !(f < 0.0f);
+            }
+            continue;
+        }
+        if (clean) {
+            // zero vertex on the evaluated row: rebuild the full state
+            lo = r + off;
+            hi = lo - 1;
+            cb = true;
+            ca = true;
+        }
+        // General step.  Rows that may change side on line j+1 (all others
+        // keep a certified side): rising, lo .. hi+1 widened by one below
+        // without cb and one above without ca; falling, lo-1 .. hi widened the
+        // same way.
         const int r0 = lo - off - (cb ? 0 : 1);
         const int r1 = hi + 1 - off + (ca ? 0 : 1);
+        if (r1 > r0 + 1) bad |= 8u;   // cannot happen: one uncertain vertex per line
         const float y = y0 + (float)r0 * hy;
         const float f0 = vertex_F(sb, sc, xx, ax, y);
-        // Usual case: one row, certified either way (|f0| > T), so the
-        // transition is r0 or r0 + 1 and both certificates carry over.
-        int lo1 = f0 > 0.0f ? r0 + 1 : r0;
-        int hi1 = lo1 - 1;
-        if (r1 > r0 || !(fabsf(f0) > T)) {
-            if (r1 > r0 + 1) bad |= 8u;   // cannot happen: one uncertain vertex per line
-            float f1 = f0;
-            if (r1 > r0) f1 = vertex_F(sb, sc, xx, ax, y + hy);
-            if (f0 <= 0.0f) lo1 = r0; else if (r1 > r0 && f1 <= 0.0f) lo1 = r1; else lo1 = r1 + 1;
-            if (r1 > r0 && f1 >= 0.0f) hi1 = r1; else if (f0 >= 0.0f) hi1 = r0; else hi1 = r0 - 1;
-            // certificates on line j+1
-            const int bv = lo1 - 1, av = hi1 + 1;
-            bool cb1 = bv < r0 ? true : ((bv == r0 ? f0 : f1) > T);
-            bool ca1 = av > r1 ? true : ((av == r0 ? f0 : f1) < -T);
-            if ((r1 > r0 && f0 < 0.0f && f1 > 0.0f) || (!cb1 && !ca1) || (bv > r1) || (av < r0)) {
-                // pattern inconsistent with the analysis: exact search instead
-                float flo2, fhi2;
-                find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo2, fhi2, bad);
-                cb1 = false;
-                ca1 = false;
-                if (hi1 == lo1 - 1) {
-                    cb1 = fhi2 > T;
-                    ca1 = flo2 < -T;
-                }
-                if (!cb1 || !ca1) {
-                    // certify the bracketing vertices directly (rare path)
-                    float yb = y0 + (float)(lo1 - 1) * hy, ya = y0 + (float)(hi1 + 1) * hy;
-                    cb1 = vertex_F(sb, sc, xx, ax, yb) > T;
-                    ca1 = vertex_F(sb, sc, xx, ax, ya) < -T;
-                    if (!cb1 || !ca1) bad |= 4u;
-                }
+        float f1 = f0;
+        if (r1 > r0) f1 = vertex_F(sb, sc, xx, ax, y + hy);
+        int lo1, hi1;
+        if (f0 <= 0.0f) lo1 = r0; else if (r1 > r0 && f1 <= 0.0f) lo1 = r1; else lo1 = r1 + 1;
+        if (r1 > r0 && f1 >= 0.0f) hi1 = r1; else if (f0 >= 0.0f) hi1 = r0; else hi1 = r0 - 1;
+        // certificates on line j+1
+        const int bv = lo1 - 1, av = hi1 + 1;
+        bool cb1 = bv < r0 ? true : ((bv == r0 ? f0 : f1) > T);
+        bool ca1 = av > r1 ? true : ((av == r0 ? f0 : f1) < -T);
+        if ((r1 > r0 && f0 < 0.0f && f1 > 0.0f) || (!cb1 && !ca1) || (bv > r1) || (av < r0)) {
+            // pattern inconsistent with the analysis: exact search instead
+            float flo2, fhi2;
+            find_transition(sb, sc, xx, ax, y0, hy, lo, lo1, hi1, flo2, fhi2, bad);
+            cb1 = false;
+            ca1 = false;
+            if (hi1 == lo1 - 1) {
+                cb1 = fhi2 > T;
+                ca1 = flo2 < -T;
             }
-            cb = cb1;
-            ca = ca1;
+            if (!cb1 || !ca1) {
+                // certify the bracketing vertices directly (rare path)
+                float yb = y0 + (float)(lo1 - 1) * hy, ya = y0 + (float)(hi1 + 1) * hy;
+                cb1 = vertex_F(sb, sc, xx, ax, yb) > T;
+                ca1 = vertex_F(sb, sc, xx, ax, ya) < -T;
+                if (!cb1 || !ca1) bad |= 4u;
+            }
         }
         emit(j, (lo < lo1 ? lo : lo1) - 1, hi > hi1 ? hi : hi1);
         lo = lo1;
         hi = hi1;
+        cb = cb1;
+        ca = ca1;
+        clean = cb && ca && hi == lo - 1;
+        r = lo - off;
     }
 }
 
