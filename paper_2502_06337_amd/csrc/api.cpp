@@ -180,7 +180,7 @@ aoresp_status HostBuf::ensure(size_t need) {
 static constexpr double kVoteTarget = 3.0e6;
 static constexpr int kCellChunk = 65536;
 static constexpr int kCorrChunk = 4096;
-static constexpr int kListChunk = 512;
+static constexpr int kListChunk = 4096;
 
 aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps, const int* npk,
                          Plan& plan) {
@@ -288,8 +288,6 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
     if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
     if (plan.maxM > 0) {
-        if ((st = w.flist.ensure(nn * sizeof(int32_t))) != AORESP_OK) return st;
-        if ((st = w.fcount.ensure((size_t)ninst * sizeof(uint32_t) + 4)) != AORESP_OK) return st;
     }
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
@@ -344,11 +342,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if (plan.maxM > 0) launch_zero_u32(w.fine.as<uint32_t>(), plan.fine_cells, s);
     for (int t = 0; t < plan.max_npk; ++t) {
         if (plan.maxM > 0) {
-            launch_zero_u32(w.fcount.as<uint32_t>(), (size_t)ninst, s);
-            launch_fine_filter(R, insts, corr_items, (int)plan.corr_items.size(), stt, t, w.flist.as<int32_t>(),
-                               w.fcount.as<uint32_t>(), s);
-            launch_fine_vote(R, insts, list_items, (int)plan.list_items.size(), stt, t, w.flist.as<int32_t>(),
-                             w.fcount.as<uint32_t>(), w.fine.as<uint32_t>(), err, plan.maxM, s);
+            launch_fine_vote(R, insts, list_items, (int)plan.list_items.size(), stt, t, w.fine.as<uint32_t>(), err,
+                             plan.maxM, s);
         }
         launch_fine_peak(w.fine.as<uint32_t>(), insts, ninst, stt, t, s);
     }
@@ -409,7 +404,7 @@ aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, st
 
 void release_workspace(Workspace& w) {
     DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.st,
-                      &w.res, &w.err, &w.flist, &w.fcount, &w.plan, &w.P, &w.Q, &w.masks};
+                      &w.res, &w.err, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
     HostBuf* hb[] = {&w.h_plan, &w.h_res, &w.h_st};
     for (HostBuf* b : hb) {

@@ -96,11 +96,8 @@ void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* 
 // vote runs in two passes: the filter lists the correspondences whose curve
 // may cross the window (list: one int32 per global column, counts: one per
 // instance, zero on entry); the vote items index positions of that list.
-void launch_fine_filter(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
-                        int32_t* list, uint32_t* counts, hipStream_t s);
 void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
-                      const int32_t* list, const uint32_t* counts, uint32_t* fine_arena, uint32_t* err, int maxM,
-                      hipStream_t s);
+                      uint32_t* fine_arena, uint32_t* err, int maxM, hipStream_t s);
 void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                       hipStream_t s);
 void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,

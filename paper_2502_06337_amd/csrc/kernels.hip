@@ -468,9 +468,16 @@ struct FineEmit {
             atomicAdd(&tile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
         }
     }
+    __device__ __forceinline__ void add(int j, int k) {
+        const int jx = mode == 0 ? j : k, jy = mode == 0 ? k : j;
+        atomicAdd(&tile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
+    }
     __device__ __forceinline__ void two(int j, int k0, int k1, bool use1) {
-        (*this)(j, k0, k0);
-        if (use1) (*this)(j, k1, k1);
+        const int lo = max(0, clo), hi = min(M - 1, chi);
+        if (hi < lo) return;
+        const unsigned span = (unsigned)(hi - lo);
+        if ((unsigned)(k0 - lo) <= span) add(j, k0);
+        if (use1 && (unsigned)(k1 - lo) <= span) add(j, k1);
     }
 };
 
@@ -510,119 +517,153 @@ __device__ __forceinline__ bool fine_may_cross(const float4& abc, uint32_t fl, c
     return !(fabs(Fc) > 1.0001 * bound + ebound);
 }
 
-// Pass 1 of the fine vote of peak `slot`: list the correspondences whose
-// curve may cross the refinement window (per instance, at its column offset).
-__global__ __launch_bounds__(256) void k_fine_filter(const ArcRecs R, const Inst* __restrict__ insts,
-                                                     const int4* __restrict__ items, const PeakState* st, int slot,
-                                                     int32_t* __restrict__ list, uint32_t* __restrict__ counts) {
-    const int4 wi = items[blockIdx.x];
-    const Inst& I = insts[wi.x];
-    if (I.M <= 0 || slot >= I.npk) return;
-    const PeakState& s = st[I.res_off + slot];
-    if (!s.valid) return;
-    FineGeom g;
-    fine_geom(s.win, I.M, g);
-    for (int64_t li0 = wi.y; li0 < wi.z; li0 += blockDim.x) {
-        const int64_t li = li0 + threadIdx.x;
-        bool hit = false;
-        if (li < wi.z) {
-            const int64_t gi = I.off + li;
-            hit = fine_may_cross(R.abc[gi], (uint32_t)R.geo[gi].w, g);
-        }
-        unsigned long long bal = __ballot(hit);
-        if (!bal) continue;
-        const int lane = threadIdx.x & 63;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&counts[wi.x], (uint32_t)__popcll(bal));
-        base = __shfl(base, 0, 64);
-        if (hit) {
-            unsigned long long below = bal & ((1ull << lane) - 1ull);
-            list[I.off + base + (uint32_t)__popcll(below)] = (int32_t)li;
-        }
-    }
+// Fine vote of peak `slot`, one work-group per range of correspondences.
+// The group lists the curves that may cross the refinement window (quick
+// reject above), computes their octant pieces in the window frame, queues one
+// entry per non-empty part (certified bodies first, searched lines after) and
+// walks the entries one per thread, so threads walk parts side by side rather
+// than each running through all eight octants of its own curve.  Candidates
+// are processed in batches of at most kFineCand; the M x M tile is flushed
+// (disk mask applied) at the end.
+constexpr int kFineThreads = 256;
+constexpr int kFineCand = 512;                 // candidate records per batch
+constexpr int kFineBody = kFineCand * 8;       // <= 8 octants x 1 body
+constexpr int kFineLine = kFineCand * 16;      // <= 8 octants x 2 searched parts
+
+size_t fine_lds_bytes(int maxM) {
+    return (size_t)maxM * maxM * 4 + (size_t)kFineCand * (16 + 16 + 16 + 16) + (size_t)kFineBody * 2 +
+           (size_t)kFineLine * 2;
 }
 
-// Pass 2: the listed curves walk the M x M fine grid in LDS, then flush.
-__global__ __launch_bounds__(256) void k_fine_vote(const ArcRecs R, const Inst* __restrict__ insts,
-                                                   const int4* __restrict__ items, const PeakState* st, int slot,
-                                                   const int32_t* __restrict__ list,
-                                                   const uint32_t* __restrict__ counts,
-                                                   uint32_t* __restrict__ fine_arena, uint32_t* __restrict__ err) {
-    extern __shared__ __align__(16) uint32_t ftile[];
+__global__ __launch_bounds__(kFineThreads) void k_fine_vote(const ArcRecs R, const Inst* __restrict__ insts,
+                                                            const int4* __restrict__ items, const PeakState* st,
+                                                            int slot, uint32_t* __restrict__ fine_arena,
+                                                            uint32_t* __restrict__ err) {
+    extern __shared__ __align__(16) uint32_t fsm[];
+    __shared__ int ncand, nbody, nline;
     const int4 wi = items[blockIdx.x];
     const Inst& I = insts[wi.x];
     if (I.M <= 0 || slot >= I.npk) return;
     const PeakState& s = st[I.res_off + slot];
     if (!s.valid) return;
-    const int64_t cnt = counts[wi.x];
-    if (wi.y >= cnt) return;
-    const int64_t c1 = wi.z < cnt ? wi.z : cnt;
     const int M = I.M;
     FineGeom g;
     fine_geom(s.win, M, g);
     const FineWin& fw = g.fw;
-    for (int t = threadIdx.x; t < M * M; t += blockDim.x) ftile[t] = 0u;
+    uint32_t* ftile = fsm;
+    float4* cabc = reinterpret_cast<float4*>(fsm + M * M);
+    int4* ccol = reinterpret_cast<int4*>(cabc + kFineCand);
+    int4* crow = ccol + kFineCand;
+    int4* cgeo = crow + kFineCand;
+    uint16_t* qbody = reinterpret_cast<uint16_t*>(cgeo + kFineCand);
+    uint16_t* qline = qbody + kFineBody;
+    int32_t* cidx = reinterpret_cast<int32_t*>(qline);   // candidate offsets, reused as queue space later
+    const int tid = threadIdx.x;
+    for (int t = tid; t < M * M; t += kFineThreads) ftile[t] = 0u;
+    if (tid == 0) ncand = 0;
     __syncthreads();
     uint32_t bad = 0;
-    for (int64_t pos = wi.y + threadIdx.x; pos < c1; pos += blockDim.x) {
-        const int64_t gi = I.off + list[I.off + pos];
-        float4 abc = R.abc[gi];
-        uint32_t fl = (uint32_t)R.geo[gi].w;
-        FineEmit em{ftile, 0, M, fw.U0, fw.V0, fw.hx, fw.hy, g.all_in, -(1 << 20), 1 << 20};
-        if (fl & kFlagRisky) {
-            for (int jy = 0; jy < M; ++jy)
-                for (int jx = 0; jx < M; ++jx) {
-                    if (!g.all_in && !em.in_disk(jx, jy)) continue;
-                    float u0 = fw.U0 + (float)jx * fw.hx, u1 = fw.U0 + (float)(jx + 1) * fw.hx;
-                    float v0 = fw.V0 + (float)jy * fw.hy, v1 = fw.V0 + (float)(jy + 1) * fw.hy;
-                    float uu0 = u0 * u0, uu1 = u1 * u1, au0 = abc.x * u0, au1 = abc.x * u1;
-                    float f0 = vertex_F(abc.y, abc.z, uu0, au0, v0);
-                    float f1 = vertex_F(abc.y, abc.z, uu1, au1, v0);
-                    float f2 = vertex_F(abc.y, abc.z, uu0, au0, v1);
-                    float f3 = vertex_F(abc.y, abc.z, uu1, au1, v1);
-                    bool le = (f0 <= 0.0f) | (f1 <= 0.0f) | (f2 <= 0.0f) | (f3 <= 0.0f);
-                    bool ge = (f0 >= 0.0f) | (f1 >= 0.0f) | (f2 >= 0.0f) | (f3 >= 0.0f);
-                    if (le && ge) atomicAdd(&ftile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
-                }
-            continue;
+    for (int64_t c0 = wi.y; c0 < wi.z; c0 += kFineThreads) {
+        // list this chunk's candidates
+        const int64_t li = c0 + tid;
+        if (li < wi.z) {
+            const int64_t gi = I.off + li;
+            if (fine_may_cross(R.abc[gi], (uint32_t)R.geo[gi].w, g)) cidx[atomicAdd(&ncand, 1)] = (int32_t)li;
         }
-        int4 colp, rowp, geo;
-        circle_pieces(abc.x, abc.y, abc.z, fl, fw.U0, fw.hx, M, fw.V0, fw.hy, M, g.margin, colp, rowp, geo);
-        int32_t cps[4] = {colp.x, colp.y, colp.z, colp.w};
-        int32_t rps[4] = {rowp.x, rowp.y, rowp.z, rowp.w};
-        int ja, jb;
-        unpack_range(geo.x, ja, jb);
-        for (int m = 0; m < 2; ++m) {
-            const int32_t* pcs = m == 0 ? cps : rps;
-            for (int p = 0; p < 4; ++p) {
-                int s0, e0, dir, slo, shi;
-                unpack_range(pcs[p], s0, e0);
-                if (s0 >= e0) continue;
-                octant_walk_info(m, p, geo, dir, slo, shi);
-                em.mode = m;
-                em.clo = (m == 1 && (p >> 1)) ? jb : -(1 << 20);
-                em.chi = (m == 1 && !(p >> 1)) ? ja - 1 : (1 << 20);
-                int2 parts[3];
-                split_piece(s0, e0, slo, shi, parts);
-                float aL = m == 0 ? abc.x : abc.y, bL = m == 0 ? abc.y : abc.x;
-                float x0 = m == 0 ? fw.U0 : fw.V0, hx = m == 0 ? fw.hx : fw.hy;
-                float y0 = m == 0 ? fw.V0 : fw.U0, hy = m == 0 ? fw.hy : fw.hx;
-                for (int q = 0; q < 3; ++q) {
-                    if (parts[q].x >= parts[q].y) continue;
-                    if (q == 1)
-                        walk_certified(aL, bL, abc.z, p >> 1, dir, abc.w, x0, hx, y0, hy, parts[q].x, parts[q].y, em,
-                                       bad);
-                    else
-                        walk_search(aL, bL, abc.z, p >> 1, x0, hx, y0, hy, parts[q].x, parts[q].y, em, bad);
-                }
+        __syncthreads();
+        const int nc = ncand;
+        __syncthreads();   // every thread has read ncand before it changes again
+        if (nc <= kFineCand - kFineThreads && c0 + kFineThreads < wi.z) continue;   // room for another chunk
+        // pieces of each candidate in the window frame; queue their parts
+        int myc[2] = {-1, -1};
+        for (int c = tid, q = 0; c < nc; c += kFineThreads, ++q) myc[q] = cidx[c];
+        __syncthreads();   // cidx is overwritten by the line queue below
+        if (tid == 0) {
+            nbody = 0;
+            nline = 0;
+        }
+        __syncthreads();
+        for (int q = 0; q < 2; ++q) {
+            const int c = tid + q * kFineThreads;
+            if (c >= nc) break;
+            const int64_t gi = I.off + myc[q];
+            const float4 abc = R.abc[gi];
+            const uint32_t fl = (uint32_t)R.geo[gi].w;
+            if (fl & kFlagRisky) {
+                // outside the walk's range of validity: every cell of the window
+                for (int jy = 0; jy < M; ++jy)
+                    for (int jx = 0; jx < M; ++jx) {
+                        float u0 = fw.U0 + (float)jx * fw.hx, u1 = fw.U0 + (float)(jx + 1) * fw.hx;
+                        float v0 = fw.V0 + (float)jy * fw.hy, v1 = fw.V0 + (float)(jy + 1) * fw.hy;
+                        float uu0 = u0 * u0, uu1 = u1 * u1, au0 = abc.x * u0, au1 = abc.x * u1;
+                        float f0 = vertex_F(abc.y, abc.z, uu0, au0, v0);
+                        float f1 = vertex_F(abc.y, abc.z, uu1, au1, v0);
+                        float f2 = vertex_F(abc.y, abc.z, uu0, au0, v1);
+                        float f3 = vertex_F(abc.y, abc.z, uu1, au1, v1);
+                        bool le = (f0 <= 0.0f) | (f1 <= 0.0f) | (f2 <= 0.0f) | (f3 <= 0.0f);
+                        bool ge = (f0 >= 0.0f) | (f1 >= 0.0f) | (f2 >= 0.0f) | (f3 >= 0.0f);
+                        if (le && ge) atomicAdd(&ftile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
+                    }
+                continue;
             }
+            int4 colp, rowp, geo;
+            circle_pieces(abc.x, abc.y, abc.z, fl, fw.U0, fw.hx, M, fw.V0, fw.hy, M, g.margin, colp, rowp, geo);
+            cabc[c] = abc;
+            ccol[c] = colp;
+            crow[c] = rowp;
+            cgeo[c] = geo;
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    const int4 pc = m == 0 ? colp : rowp;
+                    const int32_t pr = p == 0 ? pc.x : (p == 1 ? pc.y : (p == 2 ? pc.z : pc.w));
+                    int s0, e0, dir, slo, shi;
+                    unpack_range(pr, s0, e0);
+                    if (s0 >= e0) continue;
+                    octant_walk_info(m, p, geo, dir, slo, shi);
+                    int2 parts[3];
+                    split_piece(s0, e0, slo, shi, parts);
+                    const uint16_t key = (uint16_t)((c << 5) | (m << 4) | (p << 2));
+                    if (parts[1].x < parts[1].y) qbody[atomicAdd(&nbody, 1)] = key | 1u;
+                    if (parts[0].x < parts[0].y) qline[atomicAdd(&nline, 1)] = key | 0u;
+                    if (parts[2].x < parts[2].y) qline[atomicAdd(&nline, 1)] = key | 2u;
+                }
         }
+        __syncthreads();
+        // walk the queued parts, bodies first
+        const int nb = nbody, nl = nline;
+        for (int e = tid; e < nb + nl; e += kFineThreads) {
+            const int ent = e < nb ? qbody[e] : qline[e - nb];
+            const int c = ent >> 5, m = (ent >> 4) & 1, p = (ent >> 2) & 3, part = ent & 3;
+            const float4 abc = cabc[c];
+            const int4 pc = m == 0 ? ccol[c] : crow[c];
+            const int4 geo = cgeo[c];
+            const int32_t pr = p == 0 ? pc.x : (p == 1 ? pc.y : (p == 2 ? pc.z : pc.w));
+            int s0, e0, dir, slo, shi;
+            unpack_range(pr, s0, e0);
+            octant_walk_info(m, p, geo, dir, slo, shi);
+            const int2 pp = piece_part(s0, e0, slo, shi, part);
+            int ja, jb;
+            unpack_range(geo.x, ja, jb);
+            FineEmit em{ftile, m, M, fw.U0, fw.V0, fw.hx, fw.hy, g.all_in,
+                        (m == 1 && (p >> 1)) ? jb : -(1 << 20), (m == 1 && !(p >> 1)) ? ja - 1 : (1 << 20)};
+            const float aL = m == 0 ? abc.x : abc.y, bL = m == 0 ? abc.y : abc.x;
+            const float x0 = m == 0 ? fw.U0 : fw.V0, hx = m == 0 ? fw.hx : fw.hy;
+            const float y0 = m == 0 ? fw.V0 : fw.U0, hy = m == 0 ? fw.hy : fw.hx;
+            if (part == 1)
+                walk_certified(aL, bL, abc.z, p >> 1, dir, abc.w, x0, hx, y0, hy, pp.x, pp.y, em, bad);
+            else
+                walk_search(aL, bL, abc.z, p >> 1, x0, hx, y0, hy, pp.x, pp.y, em, bad);
+        }
+        __syncthreads();
+        if (tid == 0) ncand = 0;
+        __syncthreads();
     }
     if (bad) atomicOr(err, bad << 8);
-    __syncthreads();
     uint32_t* fine = fine_arena + I.fine_off + (size_t)slot * M * M;
     FineEmit em{ftile, 0, M, fw.U0, fw.V0, fw.hx, fw.hy, g.all_in, 0, 0};
-    for (int t = threadIdx.x; t < M * M; t += blockDim.x) {
+    for (int t = tid; t < M * M; t += kFineThreads) {
         uint32_t v = ftile[t];
         if (!v) continue;
         const int jy = t / M;
@@ -969,24 +1010,16 @@ void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* 
                        slot);
 }
 
-void launch_fine_filter(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
-                        int32_t* list, uint32_t* counts, hipStream_t s) {
-    if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_fine_filter, dim3((unsigned)nitems), dim3(256), 0, s, recs, insts, items, st, slot, list,
-                       counts);
-}
-
 void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
-                      const int32_t* list, const uint32_t* counts, uint32_t* fine_arena, uint32_t* err, int maxM,
-                      hipStream_t s) {
+                      uint32_t* fine_arena, uint32_t* err, int maxM, hipStream_t s) {
     if (nitems <= 0 || maxM <= 0) return;
     static bool attr = false;
     if (!attr) {
         set_lds_limit((const void*)k_fine_vote);
         attr = true;
     }
-    hipLaunchKernelGGL(k_fine_vote, dim3((unsigned)nitems), dim3(256), (size_t)maxM * maxM * 4, s, recs, insts, items,
-                       st, slot, list, counts, fine_arena, err);
+    hipLaunchKernelGGL(k_fine_vote, dim3((unsigned)nitems), dim3(kFineThreads), fine_lds_bytes(maxM), s, recs, insts,
+                       items, st, slot, fine_arena, err);
 }
 
 void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, PeakState* st, int slot,

@@ -52,7 +52,6 @@ struct Workspace {
     DevBuf abc, colp, rowp, geo;    // per global column
     DevBuf grid, fine, hist;        // arenas
     DevBuf keys, st, res, err;      // per result slot (+ err flag, vote counter)
-    DevBuf flist, fcount;           // fine-vote candidate list (per column) and counts (per instance)
     DevBuf plan;                    // instance table + work items
     DevBuf P, Q, masks;             // staging for host-pointer entry points
     HostBuf h_plan, h_res, h_st;    // pinned mirrors
