@@ -82,12 +82,11 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
 // (and, in the row pass, to the columns its quarter owns).
 struct CoarseEmit {
     uint32_t* tile;
-    int band0, lg;         // S = 2^lg + 1
-    int clo, chi;          // allowed cross indices
-    __device__ __forceinline__ uint32_t* line_of(int j) const {
-        const int jl = j - band0;
-        return tile + ((jl << lg) + jl);
-    }
+    int jofs, lg;          // S = 2^lg + 1, jofs = -band0 * S
+    int clo, chi;          // allowed cross indices (callers skip a walk when chi < clo)
+    uint32_t* sink;        // this lane's word of a scratch row that is never flushed
+    int qa = 0, qb = 0;    // clean-state cell offsets relative to clo
+    __device__ __forceinline__ uint32_t* line_of(int j) const { return tile + (((j << lg) + j) + jofs); }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
         uint32_t* line = line_of(j);
         klo = max(klo, clo);
@@ -95,13 +94,20 @@ struct CoarseEmit {
 #pragma unroll 1
         for (int k = klo; k <= khi; ++k) atomicAdd(line + k, 1u);
     }
-    // cell k0, and k1 if use1 (the common case of a walk: one or two cells)
-    __device__ __forceinline__ void two(int j, int k0, int k1, bool use1) {
-        if (chi < clo) return;   // the quarter owns no column here
-        uint32_t* line = line_of(j);
+    // cursor: line base shifted by clo
+    __device__ __forceinline__ uint32_t* start(int j, int off) {
+        qa = off - 1 - clo;
+        qb = -off - clo;
+        return line_of(j) + clo;
+    }
+    __device__ __forceinline__ uint32_t* next(uint32_t* c) const { return c + ((1 << lg) + 1); }
+    // cells r - 1 + off and, if second, r - off; a cell outside the allowed
+    // range goes to the lane's sink word instead (no divergent branch)
+    __device__ __forceinline__ void pair(uint32_t* c, int r, bool second) const {
         const unsigned span = (unsigned)(chi - clo);
-        if ((unsigned)(k0 - clo) <= span) atomicAdd(line + k0, 1u);
-        if (use1 && (unsigned)(k1 - clo) <= span) atomicAdd(line + k1, 1u);
+        const int a = r + qa, b = r + qb;
+        atomicAdd((unsigned)a <= span ? c + a : sink, 1u);
+        atomicAdd(second && (unsigned)b <= span ? c + b : sink, 1u);
     }
 };
 
@@ -126,7 +132,8 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
     uint32_t* tile = smem;
     uint32_t* rbody = smem + kTileCells + 128 + wid * (kRingBody + kRingLine);
     uint32_t* rline = rbody + kRingBody;
-    int16_t* dlim = reinterpret_cast<int16_t*>(smem + kTileCells + 128 + kWaves * (kRingBody + kRingLine));
+    uint32_t* sinkrow = smem + kTileCells + 128 + kWaves * (kRingBody + kRingLine);   // 64 words, never read
+    int16_t* dlim = reinterpret_cast<int16_t*>(sinkrow + 64);
     const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t bad = 0;
 
@@ -193,7 +200,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     octant_walk_info(mode, p, geo2, dir, slo, shi);
                     const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
                     const int sel = p >> 1;
-                    CoarseEmit em{tile, band0, lg, 0, G - 1};
+                    CoarseEmit em{tile, -band0 * S, lg, 0, G - 1, sinkrow + lane};
                     float aL = abc.x, bL = abc.y;
                     if (mode == 1) {
                         int ja, jb;
@@ -202,10 +209,13 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                         aL = abc.y;
                         bL = abc.x;
                     }
-                    if (take_b)
-                        walk_certified(aL, bL, abc.z, sel, dir, abc.w, -1.0f, h, -1.0f, h, pp.x, pp.y, em, bad);
-                    else
+                    if (em.chi < em.clo) {
+                        // this quarter owns no column in the band: nothing to vote
+                    } else if (take_b) {
+                        walk_certified<true>(aL, bL, abc.z, sel, dir, abc.w, -1.0f, h, -1.0f, h, pp.x, pp.y, em, bad);
+                    } else {
                         walk_search(aL, bL, abc.z, sel, -1.0f, h, -1.0f, h, pp.x, pp.y, em, bad);
+                    }
                 }
                 if (take_b) {
                     bh += cnt;
@@ -472,12 +482,19 @@ struct FineEmit {
         const int jx = mode == 0 ? j : k, jy = mode == 0 ? k : j;
         atomicAdd(&tile[jy * M + (jx ^ (jy & (M - 1)))], 1u);
     }
-    __device__ __forceinline__ void two(int j, int k0, int k1, bool use1) {
+    int offs = 0;
+    __device__ __forceinline__ int start(int j, int off) {
+        offs = off;
+        return j;
+    }
+    __device__ __forceinline__ int next(int j) const { return j + 1; }
+    __device__ __forceinline__ void pair(int j, int r, bool second) {
         const int lo = max(0, clo), hi = min(M - 1, chi);
         if (hi < lo) return;
         const unsigned span = (unsigned)(hi - lo);
+        const int k0 = r - 1 + offs, k1 = r - offs;
         if ((unsigned)(k0 - lo) <= span) add(j, k0);
-        if (use1 && (unsigned)(k1 - lo) <= span) add(j, k1);
+        if (second && (unsigned)(k1 - lo) <= span) add(j, k1);
     }
 };
 
@@ -962,8 +979,9 @@ __global__ void k_zero_u32(uint32_t* p, size_t count) {
 
 size_t coarse_lds_bytes() {
     // tile (bw lines of G + 1 cells, bw <= 128 beyond kTileCells) + per-wave
-    // rings (u32) + in-disk limits (2 x int16 per band line, <= 256 lines)
-    return (size_t)(kTileCells + 128) * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 2 * 2 * 256;
+    // rings (u32) + sink row + in-disk limits (2 x int16 per band line, <= 256 lines)
+    return (size_t)(kTileCells + 128) * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 64 * 4 +
+           2 * 2 * 256;
 }
 
 static void set_lds_limit(const void* fn) {

@@ -331,11 +331,18 @@ AOR_HD __forceinline__ void walk_search(float aL, float bL, float c, int sel, fl
 // to evaluate is r = lo - off (off = 1 on a falling octant), the transition
 // moves to r + (F > 0), and the voted cells of the column are r - 1 + off and,
 // if (F > 0) != off, also r - off.  Such a line costs one vertex evaluation
-// and goes to emit.two(j, first, second, second_voted).  A value |F| <= T
-// leaves one certificate missing; the next line and any zero vertex go through
-// the general step, which evaluates one or two rows and emits the range
+// and goes to emit.pair(cursor, r, second_voted).  A value |F| <= T leaves one
+// certificate missing; the next line and any zero vertex go through the
+// general step, which evaluates one or two rows and emits the range
 // min(lo) - 1 .. max(hi) of the two lines.
-template <class Emit>
+//
+// Emitter interface: start(j, off) returns a cursor for line j (and may set
+// up the pair offsets for this octant), next(cursor) advances it by a line,
+// pair(cursor, r, second) emits the clean-state cells, and emit(j, klo, khi)
+// a general range.  kLattice: every vertex coordinate y0 + k*hy is exact and
+// so are sums of them (the coarse grid), so the evaluated row's coordinate is
+// carried from line to line instead of recomputed.
+template <bool kLattice = false, class Emit>
 AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel, int dir, float T, float x0, float hx,
                                            float y0, float hy, int cs, int ce, Emit& emit, uint32_t& bad) {
     float sigma = sel ? -1.0f : 1.0f;
@@ -358,25 +365,36 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
     const int off = dir < 0 ? 1 : 0;
     bool clean = cb && ca && hi == lo - 1;
     int r = lo - off;   // the row evaluated next while clean
-    for (int j = cs; j < ce; ++j) {
+    float yr = y0 + (float)r * hy;
+    const float dy_up = (float)(1 - off) * hy, dy_dn = -(float)off * hy;   // exact: off is 0 or 1
+    auto cur = emit.start(cs, off);
+    // fresh: the clean state was left on the previous line (|F| <= T there);
+    // lo, hi, cb and ca are rebuilt from r and that value, lastf
+    bool fresh = false;
+    float lastf = 0.0f;
+    for (int j = cs; j < ce; ++j, cur = emit.next(cur)) {
         x += hx;
         xx = x * x;
         ax = sa * x;
-        float f = 0.0f;
-        if (clean) f = vertex_F(sb, sc, xx, ax, y0 + (float)r * hy);
+        // evaluated on every lane; only clean lanes use it
+        const float f = vertex_F(sb, sc, xx, ax, kLattice ? yr : y0 + (float)r * hy);
         if (clean && f != 0.0f) {
-            const int step = f > 0.0f ? 1 : 0;
-            emit.two(j, r - 1 + off, r - off, step != off);
-            r += step - off;
-            if (!(fabsf(f) > T)) {
-                // the evaluated vertex is not certified: leave the clean state
-                clean = false;
-                lo = r + off;
-                hi = lo - 1;
-                cb = !(f > 0.0f);
-                ca = !(f < 0.0f);
-            }
+            const bool up = f > 0.0f;
+            emit.pair(cur, r, up != (off != 0));
+            r += (up ? 1 : 0) - off;
+            if (kLattice) yr += up ? dy_up : dy_dn;
+            clean = fabsf(f) > T;
+            fresh = !clean;
+            lastf = f;
             continue;
+        }
+        if (fresh) {
+            // the evaluated vertex of the previous line was not certified
+            lo = r + off;
+            hi = lo - 1;
+            cb = !(lastf > 0.0f);
+            ca = !(lastf < 0.0f);
+            fresh = false;
         }
         if (clean) {
             // zero vertex on the evaluated row: rebuild the full state
@@ -384,6 +402,27 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             hi = lo - 1;
             cb = true;
             ca = true;
+        } else if (hi == lo - 1) {
+            // One certificate missing, no zero vertex: rows r0 and r0 + 1.
+            // This is the general step below with its zero-free outcomes.
+            const int r0 = lo - off - (cb ? 0 : 1);
+            const float ym = y0 + (float)r0 * hy;
+            const float f0 = vertex_F(sb, sc, xx, ax, ym);
+            const float f1 = vertex_F(sb, sc, xx, ax, ym + hy);
+            const int lo1 = f0 < 0.0f ? r0 : (f1 < 0.0f ? r0 + 1 : r0 + 2);
+            const bool cb1 = lo1 == r0 ? true : ((lo1 == r0 + 1 ? f0 : f1) > T);
+            const bool ca1 = lo1 == r0 + 2 ? true : ((lo1 == r0 ? f0 : f1) < -T);
+            if (f0 != 0.0f && f1 != 0.0f && !(f0 < 0.0f && f1 > 0.0f) && (cb1 || ca1)) {
+                emit(j, (lo < lo1 ? lo : lo1) - 1, (lo > lo1 ? lo : lo1) - 1);
+                lo = lo1;
+                hi = lo1 - 1;
+                cb = cb1;
+                ca = ca1;
+                clean = cb && ca;
+                r = lo - off;
+                if (kLattice) yr = y0 + (float)r * hy;
+                continue;
+            }
         }
         // General step.  Rows that may change side on line j+1 (all others
         // keep a certified side): rising, lo .. hi+1 widened by one below
@@ -428,6 +467,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         ca = ca1;
         clean = cb && ca && hi == lo - 1;
         r = lo - off;
+        if (kLattice) yr = y0 + (float)r * hy;
     }
 }
 
