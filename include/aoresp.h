@@ -135,6 +135,31 @@ aoresp_status aoresp_solve_debug_dev(const float* P, const float* Q, size_t n, c
 aoresp_status aoresp_stage_times_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
                                      float* ms_out, uint32_t* n_stages, void* hip_stream);
 
+/* Autotuner of the coarse vote's work split (LDS tile size and votes per
+ * work item) for one (grid, n bucket = floor(log2 n)) key.  Not a step of
+ * the paper's method: every choice gives bit-identical results (the votes are
+ * integer sums), only speed differs, and G itself is never tuned (it stays
+ * aoresp_grid_for_n(n) or the caller's value).  aoresp_autotune_dev times the
+ * coarse-vote stage of a solve of (P, Q) (device pointers, as est_rotation_dev)
+ * under each candidate, records the fastest in this device's table (used by
+ * every later plan with that key) and returns it in *chosen (may be NULL).
+ * The table lives until the process ends; save/load write and read it as JSON
+ * lines keyed by GPU architecture (entries for another architecture and
+ * malformed lines are skipped on load).  EINVAL on a NULL path or n < 2. */
+typedef struct {
+    uint32_t grid;
+    uint32_t n_bucket;
+    uint32_t tile_cells;  /* LDS tile of the coarse vote, cells (band width = tile_cells / grid lines) */
+    float vote_target;    /* votes per coarse work item */
+    float vote_ms;        /* measured coarse-vote time of this choice; -1 if not measured */
+} aoresp_tuning;
+aoresp_status aoresp_autotune_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                                  aoresp_tuning* chosen, void* hip_stream);
+aoresp_status aoresp_tuner_get(uint32_t grid, uint64_t n, aoresp_tuning* out);
+aoresp_status aoresp_tuner_save(const char* path);
+aoresp_status aoresp_tuner_load(const char* path);
+aoresp_status aoresp_tuner_clear(void);
+
 /* Request loop: continuous batching of solves under a device-memory budget.
  * aoresp_submit copies the inputs and returns at once; requests that arrive
  * while others run are admitted as memory and slots free up and run in the

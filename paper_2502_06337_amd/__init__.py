@@ -10,6 +10,7 @@ include/aoresp.h).  This package is a thin binding with the same names:
   est_rotation_batch(Ps, Qs, params)    many independent instances, batched
   coarse_grid(P, Q, G)                  the axis accumulator (device tensors)
   solve_debug(P, Q, params)             a solve plus its accumulators
+  autotune(P, Q, params)                pick the coarse vote's work split for (G, n)
   Server                                 request loop with continuous batching
 
 P and Q are (3, n) float32: numpy arrays (host entry points) or torch CUDA
@@ -26,7 +27,8 @@ from ._lib import (AorespError, Params, Result, ServerCfg, SolveParams, EBUSY, E
                    ENOMEM, ETIMEDOUT, OK)
 
 __all__ = ["est_rotation", "est_rotations_topk", "est_rotation_batch", "coarse_grid", "solve_debug",
-           "grid_for_n", "Server", "SolveParams", "AorespError", "load_library"]
+           "grid_for_n", "autotune", "tuner_get", "tuner_save", "tuner_load", "tuner_clear", "Server",
+           "SolveParams", "AorespError", "load_library"]
 
 
 def load_library():
@@ -202,3 +204,43 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def autotune(P, Q, params=None) -> dict:
+    """Time the coarse vote of a solve of (P, Q) (torch CUDA tensors) under
+    each candidate work split and keep the fastest for (G, n bucket).  Results
+    of later solves are unchanged (bit-identical); only their speed is."""
+    L = _lib.load()
+    prm = _lib._params(params)
+    P, Q = _lib._dev_soa(P), _lib._dev_soa(Q)
+    out = _lib.Tuning()
+    st = L.aoresp_autotune_dev(_vp(P), _vp(Q), P.shape[1], C.byref(prm), C.byref(out), _lib._stream_ptr(P))
+    if st != OK:
+        raise AorespError(st, "aoresp_autotune_dev")
+    return out.todict()
+
+
+def tuner_get(grid: int, n: int) -> dict:
+    out = _lib.Tuning()
+    st = _lib.load().aoresp_tuner_get(int(grid), int(n), C.byref(out))
+    if st != OK:
+        raise AorespError(st, "aoresp_tuner_get")
+    return out.todict()
+
+
+def tuner_save(path: str) -> None:
+    st = _lib.load().aoresp_tuner_save(path.encode())
+    if st != OK:
+        raise AorespError(st, "aoresp_tuner_save")
+
+
+def tuner_load(path: str) -> None:
+    st = _lib.load().aoresp_tuner_load(path.encode())
+    if st != OK:
+        raise AorespError(st, "aoresp_tuner_load")
+
+
+def tuner_clear() -> None:
+    st = _lib.load().aoresp_tuner_clear()
+    if st != OK:
+        raise AorespError(st, "aoresp_tuner_clear")

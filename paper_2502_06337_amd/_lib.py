@@ -50,6 +50,15 @@ class Result(C.Structure):
         }
 
 
+class Tuning(C.Structure):
+    _fields_ = [("grid", C.c_uint32), ("n_bucket", C.c_uint32), ("tile_cells", C.c_uint32),
+                ("vote_target", C.c_float), ("vote_ms", C.c_float)]
+
+    def todict(self) -> dict:
+        return {"grid": int(self.grid), "n_bucket": int(self.n_bucket), "tile_cells": int(self.tile_cells),
+                "vote_target": float(self.vote_target), "vote_ms": float(self.vote_ms)}
+
+
 class ServerCfg(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_uint32), ("timeout_us", C.c_uint32)]
 
@@ -73,6 +82,11 @@ SIGNATURES = {
                                          _u32p, _u32p, _u32p, _vp]),
     "aoresp_stage_times_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(C.c_float),
                                          C.POINTER(C.c_uint32), _vp]),
+    "aoresp_autotune_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(Tuning), _vp]),
+    "aoresp_tuner_get": (C.c_int, [C.c_uint32, C.c_uint64, C.POINTER(Tuning)]),
+    "aoresp_tuner_save": (C.c_int, [C.c_char_p]),
+    "aoresp_tuner_load": (C.c_int, [C.c_char_p]),
+    "aoresp_tuner_clear": (C.c_int, []),
     "aoresp_server_create": (C.c_int, [C.POINTER(ServerCfg), C.POINTER(C.c_void_p)]),
     "aoresp_submit": (C.c_int, [_vp, _fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(C.c_uint64)]),
     "aoresp_poll": (C.c_int, [_vp, C.c_uint64, C.POINTER(Result), _u8p, C.c_int64]),

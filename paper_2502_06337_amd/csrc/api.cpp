@@ -91,6 +91,8 @@ DeviceCtx* device_ctx() {
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&ctx->ws.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    if (hipStreamCreateWithFlags(&ctx->ws.cap_stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
+    init_kernel_attributes();
     DeviceCtx* raw = ctx.get();
     g_ctx[dev] = std::move(ctx);
     return raw;
@@ -174,16 +176,35 @@ aoresp_status HostBuf::ensure(size_t need) {
 }
 
 // Batch layout.  Coarse vote items: (instance, pass, band, chunk of arcs),
-// sized so that one item carries about kVoteTarget votes, ordered largest
-// first for the persistent work-groups.  Peak items: 64K cells.  Correspondence
+// sized so that one item carries about Tuning::vote_target votes, ordered
+// largest first for the persistent work-groups.  Peak items: 64K cells.  Correspondence
 // items (refinement, angle histogram): 4096 correspondences.
-static constexpr double kVoteTarget = 3.0e6;
 static constexpr int kCellChunk = 65536;
 static constexpr int kCorrChunk = 4096;
 static constexpr int kListChunk = 4096;
 
+int n_bucket(int64_t n) {
+    int b = 0;
+    while (n >= 2) {
+        n >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+Tuning tuning_for(DeviceCtx* ctx, int G, int64_t n) {
+    std::lock_guard<std::mutex> lk(ctx->tune_mu);
+    auto it = ctx->tune.find({G, n_bucket(n)});
+    return it == ctx->tune.end() ? Tuning() : it->second;
+}
+
 aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps, const int* npk,
                          Plan& plan) {
+    return build_plan_with(ctx, off, ninst, rps, npk, nullptr, plan);
+}
+
+aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps, const int* npk,
+                              const Tuning* force, Plan& plan) {
     plan = Plan();
     plan.insts.resize(ninst);
     std::vector<std::pair<double, int4>> votes;
@@ -225,11 +246,14 @@ aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const Re
         size_t lds = (size_t)rp.B * 8 + (size_t)I.npk * rp.B * 4;
         if (lds > 160 * 1024) return AORESP_EINVAL;
         if (lds > hist_lds) hist_lds = lds;
+        // coarse-vote work split: forced (tuner candidate), tuned for (G, n), or default
+        const Tuning tu = force ? *force : tuning_for(ctx, rp.G, n);
+        const int bw = coarse_band_width(rp.G, tu.tile_cells);
+        I.bw = bw;
         if (n == 0) continue;
-        int bw = coarse_band_width(rp.G);
         int nbands = (rp.G + bw - 1) / bw;
         double per_arc = 1.42 * rp.G / (2.0 * nbands);
-        int64_t chunk = (int64_t)(kVoteTarget / per_arc);
+        int64_t chunk = (int64_t)(tu.vote_target / per_arc);
         chunk = (chunk + kVoteThreads - 1) / kVoteThreads * kVoteThreads;
         if (chunk < kVoteThreads) chunk = kVoteThreads;
         if (chunk > (int64_t)1 << 27) chunk = (int64_t)1 << 27;   // ring entries hold the offset in 28 bits
@@ -266,6 +290,15 @@ aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const Re
     return AORESP_OK;
 }
 
+// Bytes of the uploaded blob: instance table (padded to 256 B), then the
+// vote, cell, correspondence and list items.
+size_t plan_blob_bytes(const Plan& plan) {
+    const size_t b_inst = plan.insts.size() * sizeof(Inst);
+    const size_t o_vote = (b_inst + 255) / 256 * 256;
+    return o_vote + (plan.vote_items.size() + plan.cell_items.size() + plan.corr_items.size() +
+                     plan.list_items.size()) * sizeof(int4) + 16;
+}
+
 aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const float* P, const float* Q,
                            uint8_t* masks, hipStream_t s, hipEvent_t* marks, uint32_t* grid_out, uint32_t* fine_out,
                            uint32_t* hist_out) {
@@ -287,15 +320,15 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
     if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
     if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
-    if (plan.maxM > 0) {
-    }
+    if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
+    if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
     const size_t o_vote = (b_inst + 255) / 256 * 256;
     const size_t o_cell = o_vote + plan.vote_items.size() * sizeof(int4);
     const size_t o_corr = o_cell + plan.cell_items.size() * sizeof(int4);
     const size_t o_list = o_corr + plan.corr_items.size() * sizeof(int4);
-    const size_t total = o_list + plan.list_items.size() * sizeof(int4) + 16;
+    const size_t total = plan_blob_bytes(plan);
     if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
     if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
     char* hb = w.h_plan.as<char>();
@@ -402,7 +435,78 @@ aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, st
     return collect_plan(w, plan, out, valid);
 }
 
+// Record the whole plan (pipeline + result copies) into one graph by stream
+// capture and launch it on s.  Every buffer is sized by a first, eager pass
+// over the allocation steps (enqueue_plan's ensure calls are then no-ops), so
+// nothing allocates while the stream is captured.  The executable graph is
+// kept in the workspace and updated in place when the next plan has the same
+// topology; otherwise it is instantiated again.
+aoresp_status launch_plan_graph(DeviceCtx* ctx, Workspace& w, const Plan& plan, const float* P, const float* Q,
+                                uint8_t* masks, hipStream_t s) {
+    aoresp_status st;
+    if ((st = reserve_plan(w, plan)) != AORESP_OK) return st;
+    if (!w.cap_stream && hipStreamCreateWithFlags(&w.cap_stream, hipStreamNonBlocking) != hipSuccess)
+        return AORESP_EDEVICE;
+    if (hipStreamBeginCapture(w.cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return AORESP_EDEVICE;
+    aoresp_status rec = enqueue_plan(ctx, w, plan, P, Q, masks, w.cap_stream);
+    if (rec == AORESP_OK) rec = fetch_plan(w, plan, w.cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(w.cap_stream, &graph);
+    if (rec != AORESP_OK || ec != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();
+        return rec != AORESP_OK ? rec : AORESP_EDEVICE;
+    }
+    bool updated = false;
+    if (w.gexec) {
+        hipGraphExecUpdateResult how;
+        hipGraphNode_t bad_node = nullptr;
+        updated = hipGraphExecUpdate(w.gexec, graph, &bad_node, &how) == hipSuccess && how == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(w.gexec);
+            w.gexec = nullptr;
+        }
+    }
+    if (!updated && hipGraphInstantiate(&w.gexec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        w.gexec = nullptr;
+        return AORESP_EDEVICE;
+    }
+    (void)hipGraphDestroy(graph);
+    AOR_HIP(hipGraphLaunch(w.gexec, s));
+    return AORESP_OK;
+}
+
+// All device and pinned buffers a plan needs (the allocation half of
+// enqueue_plan and fetch_plan).
+aoresp_status reserve_plan(Workspace& w, const Plan& plan) {
+    const size_t nn = plan.N > 0 ? (size_t)plan.N : 1;
+    aoresp_status st;
+    if ((st = w.abc.ensure(nn * sizeof(float4))) != AORESP_OK) return st;
+    if ((st = w.colp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
+    if ((st = w.rowp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
+    if ((st = w.geo.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
+    if ((st = w.grid.ensure(plan.grid_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.hist.ensure(plan.hist_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
+    if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
+    if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
+    if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
+    if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
+    if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
+    const size_t total = plan_blob_bytes(plan);
+    if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
+    if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
+    return AORESP_OK;
+}
+
 void release_workspace(Workspace& w) {
+    if (w.gexec) (void)hipGraphExecDestroy(w.gexec);
+    w.gexec = nullptr;
+    if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
+    w.cap_stream = nullptr;
     DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.st,
                       &w.res, &w.err, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
@@ -421,10 +525,9 @@ static void identity_result(aoresp_result* r, int G) {
 }
 
 // Single instance with k peaks on device pointers.
-static aoresp_status solve_dev_common(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
-                                      aoresp_result* out, uint8_t* masks, uint32_t* k_found, uint32_t* grid_out,
-                                      uint32_t* fine_out, uint32_t* hist_out, hipStream_t s,
-                                      hipEvent_t* marks = nullptr) {
+aoresp_status solve_dev_common(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
+                               aoresp_result* out, uint8_t* masks, uint32_t* k_found, uint32_t* grid_out,
+                               uint32_t* fine_out, uint32_t* hist_out, hipStream_t s, hipEvent_t* marks) {
     if (!out || (n > 0 && (!P || !Q)) || k < 1 || k > (uint32_t)kMaxPeaks) return AORESP_EINVAL;
     if (n > (size_t)INT32_MAX) return AORESP_EINVAL;
     ResolvedParams rp;
@@ -526,7 +629,7 @@ aoresp_status est_rotation(const float* P, const float* Q, size_t n, const aores
 aoresp_status est_rotation_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm, aoresp_result* out,
                                uint8_t* inlier_mask, void* hip_stream) {
     return solve_dev_common(P, Q, n, 1, prm, out, inlier_mask, nullptr, nullptr, nullptr, nullptr,
-                            (hipStream_t)hip_stream);
+                            (hipStream_t)hip_stream, nullptr);
 }
 
 aoresp_status est_rotations_topk(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
@@ -537,14 +640,14 @@ aoresp_status est_rotations_topk(const float* P, const float* Q, size_t n, uint3
 aoresp_status est_rotations_topk_dev(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
                                      aoresp_result* out, uint8_t* masks, uint32_t* k_found, void* hip_stream) {
     return solve_dev_common(P, Q, n, k, prm, out, masks, k_found, nullptr, nullptr, nullptr,
-                            (hipStream_t)hip_stream);
+                            (hipStream_t)hip_stream, nullptr);
 }
 
 aoresp_status aoresp_solve_debug_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
                                      aoresp_result* out, uint8_t* inlier_mask, uint32_t* grid_out, uint32_t* fine_out,
                                      uint32_t* hist_out, void* hip_stream) {
     return solve_dev_common(P, Q, n, 1, prm, out, inlier_mask, nullptr, grid_out, fine_out, hist_out,
-                            (hipStream_t)hip_stream);
+                            (hipStream_t)hip_stream, nullptr);
 }
 
 aoresp_status aoresp_coarse_grid_dev(const float* P, const float* Q, size_t n, uint32_t G, uint32_t* grid,

@@ -1,7 +1,9 @@
 // Batched solves (est_rotation_batch): many independent instances of uneven
 // size in one launch per stage.  Every stage runs over the instance table;
 // the coarse vote uses persistent work-groups pulling (instance, pass, band,
-// chunk) items ordered largest first.  Instance b's result is bit-identical
+// chunk) items ordered largest first.  The stage sequence of a batch is
+// captured into one hipGraph and launched as a whole (the executable graph is
+// updated in place for the next batch).  Instance b's result is bit-identical
 // to est_rotation on its own columns with the same parameters: the kernels
 // are the same and each instance only touches its own grid, windows and
 // histograms.
@@ -56,11 +58,13 @@ static aoresp_status batch_common(const float* P, const float* Q, const uint64_t
     }
     Plan plan;
     if ((st = build_plan(ctx, offs.data(), (int)batch, rps.data(), npk.data(), plan)) != AORESP_OK) return st;
-    if ((st = enqueue_plan(ctx, ctx->ws, plan, dP, dQ, dM, s)) != AORESP_OK) return st;
+    // the whole batched pipeline as one captured graph
+    if ((st = launch_plan_graph(ctx, w, plan, dP, dQ, dM, s)) != AORESP_OK) return st;
     if (host && masks && N && hipMemcpyAsync(masks, w.masks.ptr, N, hipMemcpyDeviceToHost, s) != hipSuccess)
         return AORESP_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return AORESP_EDEVICE;
     std::vector<int> valid;
-    if ((st = finish_plan(ctx->ws, plan, out, valid, s)) != AORESP_OK) return st;
+    if ((st = collect_plan(w, plan, out, valid)) != AORESP_OK) return st;
     // instances with fewer than two correspondences or no vote: R = I
     for (uint32_t b = 0; b < batch; ++b) {
         if (off[b + 1] - off[b] < 2 || !valid[b]) {

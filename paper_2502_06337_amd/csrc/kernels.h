@@ -46,6 +46,7 @@ struct Inst {
     int32_t n;            // correspondences
     int32_t G, M, w, B, rad, npk, res_off;
     float tau;
+    int32_t bw;           // coarse band width (cell lines per LDS tile), a power of two
     int64_t grid_off;     // u32 offset of its G*G coarse grid in the grid arena
     int64_t fine_off;     // u32 offset of its npk fine grids (M*M each)
     int64_t hist_off;     // u32 offset of its npk histograms (B each)
@@ -72,13 +73,16 @@ struct PeakState {
 };
 
 // Coarse LDS band width (cell lines) for a G x G grid.
-__host__ __device__ inline int coarse_band_width(int G) {
-    int bw = kTileCells / G;
+// Band width of a coarse tile of `tile_cells` cells (at most kTileCells) for
+// a G x G grid: a power of two, at most G.
+__host__ __device__ inline int coarse_band_width(int G, int tile_cells = kTileCells) {
+    int bw = tile_cells / G;
     if (bw > G) bw = G;
     if (bw < 1) bw = 1;
     return bw;
 }
 size_t coarse_lds_bytes();
+void init_kernel_attributes();   // once per device, before the first launch
 
 void launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
 void launch_arc_setup(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, ArcRecs recs,

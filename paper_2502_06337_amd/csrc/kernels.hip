@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         const int G = I.G;
         const int mode = wi.y & 1;
         const int band = wi.y >> 1;
-        const int bw = coarse_band_width(G);
+        const int bw = I.bw;
         const int band0 = band * bw;
         const int bwb = (band0 + bw <= G) ? bw : (G - band0);
         const int S = G + 1;                 // tile line stride
@@ -989,6 +989,14 @@ static void set_lds_limit(const void* fn) {
         (void)hipGetLastError();
 }
 
+void init_kernel_attributes() {
+    // the kernels that take more than the default dynamic LDS; done once per
+    // device before any launch (and so outside any stream capture)
+    set_lds_limit((const void*)k_vote);
+    set_lds_limit((const void*)k_fine_vote);
+    set_lds_limit((const void*)k_angle_hist);
+}
+
 void launch_zero_u32(uint32_t* p, size_t count, hipStream_t s) {
     if (!count) return;
     size_t blocks = (count + 255) / 256;
@@ -1005,11 +1013,6 @@ void launch_arc_setup(const float* P, const float* Q, int64_t N, const Inst* ins
 void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, uint32_t* counter,
                  uint32_t* grid_arena, uint32_t* err, int blocks, hipStream_t s) {
     if (nitems <= 0) return;
-    static bool attr = false;
-    if (!attr) {
-        set_lds_limit((const void*)k_vote);
-        attr = true;
-    }
     if (blocks > nitems) blocks = nitems;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_vote, dim3((unsigned)blocks), dim3(kVoteThreads), coarse_lds_bytes(), s, recs, insts, items,
@@ -1031,11 +1034,6 @@ void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* 
 void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
                       uint32_t* fine_arena, uint32_t* err, int maxM, hipStream_t s) {
     if (nitems <= 0 || maxM <= 0) return;
-    static bool attr = false;
-    if (!attr) {
-        set_lds_limit((const void*)k_fine_vote);
-        attr = true;
-    }
     hipLaunchKernelGGL(k_fine_vote, dim3((unsigned)nitems), dim3(kFineThreads), fine_lds_bytes(maxM), s, recs, insts,
                        items, st, slot, fine_arena, err);
 }
@@ -1048,11 +1046,6 @@ void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, 
 void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
                        const PeakState* st, uint32_t* hist_arena, size_t lds_bytes, hipStream_t s) {
     if (nitems <= 0) return;
-    static bool attr = false;
-    if (!attr) {
-        set_lds_limit((const void*)k_angle_hist);
-        attr = true;
-    }
     hipLaunchKernelGGL(k_angle_hist, dim3((unsigned)nitems), dim3(512), lds_bytes, s, P, Q, N, insts, items, st,
                        hist_arena);
 }

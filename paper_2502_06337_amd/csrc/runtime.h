@@ -56,6 +56,8 @@ struct Workspace {
     DevBuf P, Q, masks;             // staging for host-pointer entry points
     HostBuf h_plan, h_res, h_st;    // pinned mirrors
     hipStream_t stream = nullptr;   // internal stream for host-pointer calls
+    hipStream_t cap_stream = nullptr;   // stream that batched plans are captured on
+    hipGraphExec_t gexec = nullptr;     // last captured plan, updated in place when the topology repeats
 };
 
 // A batch laid out for the kernels.
@@ -69,6 +71,15 @@ struct Plan {
     size_t hist_lds = 0;
 };
 
+// Work split of the coarse vote for one (G, n bucket): LDS tile cells and
+// votes per work item.  Any choice gives the same grid; only speed differs.
+struct Tuning {
+    int tile_cells = kTileCells;
+    double vote_target = 3.0e6;
+    float vote_ms = -1.0f;   // measured coarse-vote time of this choice (-1: default, not measured)
+};
+int n_bucket(int64_t n);     // floor(log2(n)), 0 for n < 2
+
 struct DeviceCtx {
     int device = 0;
     int cu_count = 256;
@@ -77,7 +88,11 @@ struct DeviceCtx {
     std::map<int, AngleTables> angle;   // by B
     std::map<int, int16_t*> disk;       // by G
     std::mutex table_mu;
+    std::map<std::pair<int, int>, Tuning> tune;   // by (G, n bucket)
+    std::mutex tune_mu;
 };
+
+Tuning tuning_for(DeviceCtx* ctx, int G, int64_t n);
 
 DeviceCtx* device_ctx();            // context of the current HIP device
 const AngleTables* angle_tables(DeviceCtx* ctx, int B);
@@ -86,6 +101,13 @@ const int16_t* disk_table(DeviceCtx* ctx, int G);
 // Instance b owns global columns [off[b], off[b+1]).
 aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rp, const int* npk,
                          Plan& plan);
+// The same with the coarse-vote work split forced (autotuner candidates).
+aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rp, const int* npk,
+                              const Tuning* force, Plan& plan);
+// Single solve on device pointers with optional stage events (kNumStages + 1).
+aoresp_status solve_dev_common(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
+                               aoresp_result* out, uint8_t* masks, uint32_t* k_found, uint32_t* grid_out,
+                               uint32_t* fine_out, uint32_t* hist_out, hipStream_t s, hipEvent_t* marks);
 
 // Stage boundaries recorded when `marks` is non-null (kNumStages + 1 events).
 enum Stage { kStageSetup = 0, kStageCoarse, kStagePeak, kStageFine, kStageAngle, kStageInliers, kNumStages };
@@ -104,5 +126,12 @@ aoresp_status collect_plan(Workspace& w, const Plan& plan, aoresp_result* out, s
 aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, std::vector<int>& valid,
                           hipStream_t s);
 void release_workspace(Workspace& w);
+// Allocation half of enqueue_plan + fetch_plan; size of the uploaded blob.
+aoresp_status reserve_plan(Workspace& w, const Plan& plan);
+size_t plan_blob_bytes(const Plan& plan);
+// enqueue_plan + fetch_plan captured into one hipGraph and launched on s
+// (caller holds ctx->mu; no stage marks or debug copies).
+aoresp_status launch_plan_graph(DeviceCtx* ctx, Workspace& w, const Plan& plan, const float* P, const float* Q,
+                                uint8_t* masks, hipStream_t s);
 
 }  // namespace aoresp

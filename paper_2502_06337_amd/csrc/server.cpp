@@ -171,12 +171,12 @@ struct aoresp_server {
         if (hipMemcpyAsync(p.P.ptr, hp, 3 * N * 4, hipMemcpyHostToDevice, p.stream) != hipSuccess) return AORESP_EDEVICE;
         if (hipMemcpyAsync(p.Q.ptr, hq, 3 * N * 4, hipMemcpyHostToDevice, p.stream) != hipSuccess) return AORESP_EDEVICE;
         if ((st = build_plan(ctx, off.data(), nb, rps.data(), npk.data(), p.plan)) != AORESP_OK) return st;
-        if ((st = enqueue_plan(ctx, p.ws, p.plan, p.P.as<float>(), p.Q.as<float>(), p.masks.as<uint8_t>(), p.stream)) !=
-            AORESP_OK)
+        // the step's pipeline and result copies as one captured graph
+        if ((st = launch_plan_graph(ctx, p.ws, p.plan, p.P.as<float>(), p.Q.as<float>(), p.masks.as<uint8_t>(),
+                                    p.stream)) != AORESP_OK)
             return st;
         if (hipMemcpyAsync(p.hmask.ptr, p.masks.ptr, N, hipMemcpyDeviceToHost, p.stream) != hipSuccess)
             return AORESP_EDEVICE;
-        if ((st = fetch_plan(p.ws, p.plan, p.stream)) != AORESP_OK) return st;
         if (hipEventRecord(p.done_ev, p.stream) != hipSuccess) return AORESP_EDEVICE;
         return AORESP_OK;
     }

@@ -185,6 +185,29 @@ def test_batch_matches_single_solves(aor, orc):
         assert_result_equal(outs[t], r_or)
 
 
+def test_batch_graph_relaunched_with_changing_batches(aor):
+    """Batches run as one captured graph that is updated in place or rebuilt
+    from call to call.  Several batches of different composition, with eager
+    single solves and synchronisations in between, must each equal the
+    one-at-a-time results."""
+    rng = np.random.default_rng(7)
+    for rep in range(4):
+        nb = [3, 5, 3, 8][rep]
+        sizes = [int(x) for x in rng.integers(300, 5000, nb)]
+        insts = [synth.make_instance(n, 7000 + 37 * rep + t, outlier_rate=0.85) for t, n in enumerate(sizes)]
+        P = np.concatenate([i.P for i in insts], axis=1)
+        Q = np.concatenate([i.Q for i in insts], axis=1)
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+        prm = aor.SolveParams(angle_bins=360, refine_grid=(16 if rep % 2 else 0))
+        outs, mask, _ = aor.est_rotation_batch(dev(P), dev(Q), off, prm)
+        mask = mask.cpu().numpy()
+        torch.cuda.synchronize()
+        for t in range(nb):
+            r1, m1, _ = aor.est_rotation(insts[t].P, insts[t].Q, prm)
+            assert_result_equal(outs[t], r1)
+            assert np.array_equal(mask[off[t]:off[t + 1]], m1), (rep, t)
+
+
 # ------------------------------------------------------ full size, sampled
 def test_paper_scale_sampled_parity(aor, orc):
     """n = 1e6, G = 1024 + 64x64 refinement, B = 3600 (the benchmark's launch
