@@ -10,7 +10,12 @@ histogram, Rodrigues, inlier mask) with P and Q already resident in HBM.
 
 Prints one JSON line: Mcorr/s, the roofline of the dominant kernel (coarse
 vote) measured with HIP events on the launch stream, and the CPU oracle timed
-on a bounded sample of the same workload.
+on a bounded sample of the same workload.  Beside the headline it reports the
+batched workload (256 instances, n log-uniform in [1e3, 1e5]: one batched
+call against a one-at-a-time loop) and a served stream (Poisson arrivals at
+2000 requests/s, n log-uniform in [1e3, 1e6], 90% outliers, 8 GiB budget,
+shortened to --serve-seconds: the request loop against a one-at-a-time loop
+fed the same arrivals).
 """
 from __future__ import annotations
 
@@ -44,15 +49,104 @@ def cpu_model() -> str:
     return platform.processor() or "unknown"
 
 
+def bench_batch(aor, synth, torch, reps: int) -> dict:
+    """256 instances, n log-uniform in [1e3, 1e5], outlier rate in [0.5, 0.95],
+    sigma in [0.001, 0.02]; G per instance = aoresp_grid_for_n(n).  One
+    batched call (a captured graph over all instances) against a loop of
+    one-at-a-time device solves over the same inputs, both on resident data."""
+    insts = synth.batch_instances(256, synth.config_seed(4, 0))
+    sizes = [i.n for i in insts]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    dev = torch.device("cuda:0")
+    P = torch.from_numpy(np.concatenate([i.P for i in insts], axis=1)).to(dev)
+    Q = torch.from_numpy(np.concatenate([i.Q for i in insts], axis=1)).to(dev)
+    Ps = [P[:, int(off[b]):int(off[b + 1])].contiguous() for b in range(len(sizes))]
+    Qs = [Q[:, int(off[b]):int(off[b + 1])].contiguous() for b in range(len(sizes))]
+    prm = aor.SolveParams(angle_bins=360)
+    outs, _, _ = aor.est_rotation_batch(P, Q, off, prm, want_mask=False)
+    for b in range(len(sizes)):
+        aor.est_rotation(Ps[b], Qs[b], prm, want_mask=False)
+    torch.cuda.synchronize()
+    tb, tl = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        aor.est_rotation_batch(P, Q, off, prm, want_mask=False)
+        torch.cuda.synchronize()
+        tb.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        for b in range(len(sizes)):
+            aor.est_rotation(Ps[b], Qs[b], prm, want_mask=False)
+        torch.cuda.synchronize()
+        tl.append(time.perf_counter() - t0)
+    total = int(off[-1])
+    bt, lt = min(tb), min(tl)
+    grids = sorted({int(o["grid"]) for o in outs})
+    return {"workload": "256 instances, n log-U[1e3,1e5], rho U[0.5,0.95], sigma U[0.001,0.02], B=360",
+            "total_n": total, "grids": grids, "batched_ms": round(bt * 1e3, 3), "plain_loop_ms": round(lt * 1e3, 3),
+            "speedup": round(lt / bt, 3), "batched_Mcorr_s": round(total / bt / 1e6, 2),
+            "plain_Mcorr_s": round(total / lt / 1e6, 2)}
+
+
+def bench_serve(aor, synth, seconds: float) -> dict:
+    """Poisson arrivals at 2000 requests/s for `seconds`, each request a
+    single rotation with n log-uniform in [1e3, 1e6] and 90% outliers (a pool
+    of 48 generated problems is reused), through the request loop under an
+    8 GiB budget, and through a one-at-a-time host-pointer loop that takes the
+    same arrivals (a request waits until the previous one finished).
+    Latency = completion - arrival."""
+    arrivals = synth.poisson_arrivals(2000.0, seconds, synth.config_seed(5, 0))
+    sizes = synth.log_uniform_sizes(48, synth.config_seed(5, 0), 1e3, 1e6)
+    pool = [synth.make_instance(int(n), synth.config_seed(5, 1 + k), outlier_rate=0.9, sigma=0.01)
+            for k, n in enumerate(sizes)]
+    prm = aor.SolveParams(angle_bins=360)
+    nreq = len(arrivals)
+    # served
+    srv = aor.Server(hbm_budget_bytes=8 << 30, max_slots=256)
+    ids = []
+    t0 = time.perf_counter()
+    for i, a in enumerate(arrivals):
+        wait = t0 + a - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        inst = pool[i % len(pool)]
+        ids.append(srv.submit(inst.P, inst.Q, prm))
+    for rid in ids:
+        srv.poll(rid, timeout_us=-1, want_mask=False)
+    served_wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    # one at a time
+    lat = []
+    t0 = time.perf_counter()
+    for i, a in enumerate(arrivals):
+        wait = t0 + a - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        inst = pool[i % len(pool)]
+        aor.est_rotation(inst.P, inst.Q, prm, want_mask=False)
+        lat.append(time.perf_counter() - (t0 + a))
+    plain_wall = time.perf_counter() - t0
+    lat = np.array(lat) * 1e6
+    return {"workload": f"Poisson 2000 req/s x {seconds:g} s, n log-U[1e3,1e6], rho=0.9, sigma=0.01, B=360, 8 GiB",
+            "requests": nreq, "served": {"p50_us": round(st["p50_us"], 1), "p99_us": round(st["p99_us"], 1),
+                                         "req_per_s": round(nreq / served_wall, 1), "completed": int(st["completed"])},
+            "plain_loop": {"p50_us": round(float(np.percentile(lat, 50)), 1),
+                           "p99_us": round(float(np.percentile(lat, 99)), 1),
+                           "req_per_s": round(nreq / plain_wall, 1)}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_CORR)
-    ap.add_argument("--cpu-sample", type=int, default=1200,
+    ap.add_argument("--cpu-sample", type=int, default=3000,
                     help="correspondences timed with the CPU oracle (0 = skip)")
     ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--no-tune", action="store_true", help="skip the work-split autotuner")
+    ap.add_argument("--batch-reps", type=int, default=3, help="batched workload repetitions (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0, help="served stream length (0 = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -77,6 +171,10 @@ def main() -> int:
     Q = torch.from_numpy(inst.Q).to(dev)
     prm = aor.SolveParams(grid=G, refine_grid=M, angle_bins=B, inlier_thresh=0.05)
     torch.cuda.synchronize()
+
+    # work split of the coarse vote for this (G, n): chosen by the autotuner
+    # (results are identical for every choice; only speed differs)
+    tuning = None if args.no_tune else aor.autotune(P, Q, prm)
 
     # correctness of the measured path on this input (mask kept on device)
     res, mask, st = aor.est_rotation(P, Q, prm)
@@ -145,6 +243,9 @@ def main() -> int:
                      "ops_per_vote": OPS_PER_VOTE},
         "cpu_baseline": cpu,
         "stages_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_avg)},
+        "tuning": tuning,
+        "batch": bench_batch(aor, synth, torch, args.batch_reps) if args.batch_reps > 0 else None,
+        "serve": bench_serve(aor, synth, args.serve_seconds) if args.serve_seconds > 0 else None,
         "rotation_error_deg": round(re_gpu, 4),
         "status": int(st),
         "n_inliers": res["n_inliers"],
