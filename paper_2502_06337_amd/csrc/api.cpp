@@ -179,7 +179,7 @@ aoresp_status HostBuf::ensure(size_t need) {
 // sized so that one item carries about Tuning::vote_target votes, ordered
 // largest first for the persistent work-groups.  Peak items: 64K cells.  Correspondence
 // items (refinement, angle histogram): 4096 correspondences.
-static constexpr int kCellChunk = 65536;
+static constexpr int kCellChunk = 8192;
 static constexpr int kCorrChunk = 4096;
 static constexpr int kListChunk = 4096;
 
@@ -320,6 +320,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
     if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
     if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
+    if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
     if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
     if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
     // instance table and work items, uploaded as one blob
@@ -386,7 +387,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
                       plan.hist_lds, s);
     for (int t = 0; t < plan.max_npk; ++t) launch_angle_peak(w.hist.as<uint32_t>(), insts, ninst, stt, t, res, s);
     mark(5);
-    launch_inliers(P, Q, N, insts, ninst, stt, res, masks, s);
+    launch_inliers(P, Q, N, insts, ninst, stt, res, plan.nres, masks, w.icount.as<uint32_t>(), s);
     mark(6);
     if (ninst == 1) {
         const Inst& I = plan.insts[0];
@@ -494,6 +495,7 @@ aoresp_status reserve_plan(Workspace& w, const Plan& plan) {
     if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
     if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
     if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
+    if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
     if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
     if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
     const size_t total = plan_blob_bytes(plan);
@@ -508,7 +510,7 @@ void release_workspace(Workspace& w) {
     if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
     w.cap_stream = nullptr;
     DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.st,
-                      &w.res, &w.err, &w.plan, &w.P, &w.Q, &w.masks};
+                      &w.res, &w.err, &w.icount, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
     HostBuf* hb[] = {&w.h_plan, &w.h_res, &w.h_st};
     for (HostBuf* b : hb) {

@@ -21,6 +21,7 @@ constexpr uint32_t kFlagLineDown = 8u;    // line whose cross coordinate decreas
 constexpr int kMaxPeaks = 8;
 constexpr int kTileCells = 32768;         // u32 cells of one coarse LDS band (128 KiB)
 constexpr int kVoteThreads = 1024;
+constexpr int kCountSlots = 64;   // partial inlier counters per result
 constexpr int kRingBody = 128;     // per-wave ring of certified parts: < 64 left over + <= 64 appended
 constexpr int kRingLine = 256;     // per-wave ring of searched parts: < 64 left over + <= 128 appended
 
@@ -109,6 +110,6 @@ void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* in
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                        aoresp_result* res, hipStream_t s);
 void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, const PeakState* st,
-                    aoresp_result* res, uint8_t* masks, hipStream_t s);
+                    aoresp_result* res, int nres, uint8_t* masks, uint32_t* partial, hipStream_t s);
 
 }  // namespace aoresp

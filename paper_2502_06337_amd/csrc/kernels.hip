@@ -400,20 +400,28 @@ __global__ __launch_bounds__(256) void k_peak(const uint32_t* __restrict__ grid_
     const int G = I.G;
     const PeakState* prev = st + I.res_off;
     unsigned long long best = 0ull;
-    for (int c = wi.y + threadIdx.x; c < wi.z; c += blockDim.x) {
-        uint32_t v = a[c];
-        if (v == 0u) continue;
-        if (slot > 0) {
-            int ix = c % G, iy = c / G;
-            bool sup = false;
-            for (int t = 0; t < slot && !sup; ++t) {
-                uint32_t pc = prev[t].peak_cell;
-                sup = suppressed(G, I.rad, (int)(pc % (uint32_t)G), (int)(pc / (uint32_t)G), ix, iy);
+    // four cells per 16-byte load (item bounds and grid offsets are multiples of 4)
+    const uint4* a4 = reinterpret_cast<const uint4*>(a);
+    for (int c4 = (wi.y >> 2) + threadIdx.x; c4 < (wi.z >> 2); c4 += blockDim.x) {
+        const uint4 q = a4[c4];
+        const uint32_t vv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t v = vv[u];
+            const int c = 4 * c4 + u;
+            if (v == 0u) continue;
+            if (slot > 0) {
+                int ix = c % G, iy = c / G;
+                bool sup = false;
+                for (int t = 0; t < slot && !sup; ++t) {
+                    uint32_t pc = prev[t].peak_cell;
+                    sup = suppressed(G, I.rad, (int)(pc % (uint32_t)G), (int)(pc / (uint32_t)G), ix, iy);
+                }
+                if (sup) continue;
             }
-            if (sup) continue;
+            unsigned long long k = ((unsigned long long)v << 32) | (unsigned long long)(~(uint32_t)c);
+            best = k > best ? k : best;
         }
-        unsigned long long k = ((unsigned long long)v << 32) | (unsigned long long)(~(uint32_t)c);
-        best = k > best ? k : best;
     }
     best = block_max_u64(best, red);
     if (threadIdx.x == 0 && best) atomicMax(&keys[I.res_off + slot], best);
@@ -905,10 +913,15 @@ __global__ __launch_bounds__(1024) void k_angle_peak(const uint32_t* __restrict_
 // ||R p - q||^2 <= tau^2 per correspondence (Eq. (1)); masks[slot*N + i] if
 // masks is non-null; counts land in res[..].n_inliers (one atomic per block
 // and slot when the block lies in one instance, else one per wave or lane).
+// Inlier counts: a block that lies inside one instance adds its count to one
+// of kCountSlots partial counters of the result (chosen by block index), so
+// that no single address takes one atomic per block; k_inliers_total sums
+// the partials into the result.  Blocks that straddle two instances add per
+// correspondence straight into the result.
 __global__ __launch_bounds__(256) void k_inliers(const float* __restrict__ P, const float* __restrict__ Q,
                                                  int64_t N, const Inst* __restrict__ insts, int ninst,
                                                  const PeakState* st, aoresp_result* res,
-                                                 uint8_t* __restrict__ masks) {
+                                                 uint8_t* __restrict__ masks, uint32_t* __restrict__ partial) {
     __shared__ uint32_t cnt[kMaxPeaks];
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t first = (int64_t)blockIdx.x * blockDim.x;
@@ -964,8 +977,18 @@ __global__ __launch_bounds__(256) void k_inliers(const float* __restrict__ P, co
     if (block_uniform) {
         __syncthreads();
         if (threadIdx.x < npk && cnt[threadIdx.x])
-            atomicAdd(&res[insts[bfirst].res_off + threadIdx.x].n_inliers, cnt[threadIdx.x]);
+            atomicAdd(&partial[(size_t)(insts[bfirst].res_off + threadIdx.x) * kCountSlots +
+                               (blockIdx.x & (kCountSlots - 1))],
+                      cnt[threadIdx.x]);
     }
+}
+
+__global__ void k_inliers_total(const uint32_t* __restrict__ partial, int nres, aoresp_result* res) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nres) return;
+    uint32_t sum = 0u;
+    for (int k = 0; k < kCountSlots; ++k) sum += partial[(size_t)r * kCountSlots + k];
+    res[r].n_inliers += sum;
 }
 
 __global__ void k_zero_u32(uint32_t* p, size_t count) {
@@ -1056,10 +1079,12 @@ void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst,
 }
 
 void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, const PeakState* st,
-                    aoresp_result* res, uint8_t* masks, hipStream_t s) {
+                    aoresp_result* res, int nres, uint8_t* masks, uint32_t* partial, hipStream_t s) {
     if (N <= 0) return;
+    launch_zero_u32(partial, (size_t)nres * kCountSlots, s);
     hipLaunchKernelGGL(k_inliers, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, Q, N, insts, ninst, st, res,
-                       masks);
+                       masks, partial);
+    hipLaunchKernelGGL(k_inliers_total, dim3((unsigned)((nres + 63) / 64)), dim3(64), 0, s, partial, nres, res);
 }
 
 }  // namespace aoresp

@@ -52,6 +52,7 @@ struct Workspace {
     DevBuf abc, colp, rowp, geo;    // per global column
     DevBuf grid, fine, hist;        // arenas
     DevBuf keys, st, res, err;      // per result slot (+ err flag, vote counter)
+    DevBuf icount;                  // partial inlier counters (kCountSlots per result slot)
     DevBuf plan;                    // instance table + work items
     DevBuf P, Q, masks;             // staging for host-pointer entry points
     HostBuf h_plan, h_res, h_st;    // pinned mirrors
