@@ -38,6 +38,35 @@ ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12   # non-packed fp32 lane ops/s: 256 CU
 STAGES = ["setup", "coarse_vote", "peak", "refine", "angle", "inliers"]
 
 
+KERNEL_SOURCES = ["paper_2502_06337_amd/csrc/kernels.hip", "paper_2502_06337_amd/csrc/kernels.h",
+                  "paper_2502_06337_amd/csrc/walker.h", "paper_2502_06337_amd/csrc/geometry.h"]
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_vote_hbm_traffic_c2.json")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per coarse-vote launch from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the same counters on a copy of known
+    size), or None if the summary is missing or was taken on other kernel
+    sources."""
+    try:
+        with open(TRAFFIC_SUMMARY) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    return d.get("bytes_per_launch")
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -147,6 +176,8 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="skip the work-split autotuner")
     ap.add_argument("--batch-reps", type=int, default=3, help="batched workload repetitions (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="served stream length (0 = skip)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -163,6 +194,14 @@ def main() -> int:
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe << 20, "copies": 5}), flush=True)
+        return 0
     L = aor.load_library()
     dev = torch.device("cuda:0")
 
@@ -238,7 +277,7 @@ def main() -> int:
         "config": {"workload": "plain single solve, n=1e6, 90% outliers, G=1024 + 64x64 refinement, B=3600",
                    "n": args.n, "grid": G, "refine": M, "angle_bins": B, "seed": args.seed},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
-                     "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                      "kernel": "k_vote", "kernel_ms": round(stage_avg[1], 4), "votes": votes,
                      "ops_per_vote": OPS_PER_VOTE},
         "cpu_baseline": cpu,
