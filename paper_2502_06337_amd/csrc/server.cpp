@@ -28,9 +28,51 @@ using Clock = std::chrono::steady_clock;
 
 namespace {
 
+// Pinned host blocks in power-of-two size classes, kept for reuse until the
+// server is destroyed: a request's inputs are copied once, at submit, into a
+// pinned block, and uploaded from there without a staging copy.
+class PinnedPool {
+  public:
+    ~PinnedPool() {
+        for (auto& fl : free_)
+            for (void* b : fl) (void)hipHostFree(b);
+    }
+    // A block of at least `bytes`; *cls receives its class (for put).
+    void* get(size_t bytes, int* cls) {
+        int c = 16;   // 64 KiB minimum
+        while (((size_t)1 << c) < bytes) ++c;
+        *cls = c;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            if (c < (int)free_.size() && !free_[c].empty()) {
+                void* b = free_[c].back();
+                free_[c].pop_back();
+                return b;
+            }
+        }
+        void* b = nullptr;
+        if (hipHostMalloc(&b, (size_t)1 << c, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return b;
+    }
+    void put(void* b, int cls) {
+        if (!b) return;
+        std::lock_guard<std::mutex> lk(mu_);
+        if ((int)free_.size() <= cls) free_.resize(cls + 1);
+        free_[cls].push_back(b);
+    }
+
+  private:
+    std::mutex mu_;
+    std::vector<std::vector<void*>> free_;
+};
+
 struct Request {
     uint64_t id = 0;
-    std::vector<float> P, Q;     // host copies (3, n)
+    float* host = nullptr;       // pinned copy: P rows x, y, z then Q rows x, y, z (n floats each)
+    int host_cls = 0;
     size_t n = 0;
     ResolvedParams rp{};
     size_t bytes = 0;            // device bytes while admitted
@@ -49,7 +91,7 @@ struct Pipeline {
     Workspace ws;
     hipStream_t stream = nullptr;
     DevBuf P, Q, masks;          // batch inputs / outputs on the device
-    HostBuf hP, hQ, hmask;       // pinned staging
+    HostBuf hmask;               // pinned mask staging
     std::vector<std::shared_ptr<Request>> reqs;
     Plan plan;
     hipEvent_t done_ev = nullptr;
@@ -78,6 +120,7 @@ struct aoresp_server {
     bool stopping = false;
     size_t bytes_in_flight = 0;
     Pipeline pipes[2];
+    PinnedPool pool;
     std::thread thr;
     // stats
     std::vector<double> lat_us;
@@ -99,10 +142,8 @@ struct aoresp_server {
         }
         if (r->t_submit < t_first) t_first = r->t_submit;
         t_last = now;
-        r->P.clear();
-        r->P.shrink_to_fit();
-        r->Q.clear();
-        r->Q.shrink_to_fit();
+        pool.put(r->host, r->host_cls);
+        r->host = nullptr;
     }
 
     // Launch one batch on pipeline p from the head of the queue (mu held).
@@ -153,23 +194,23 @@ struct aoresp_server {
         }
         const size_t N = (size_t)off[nb];
         aoresp_status st;
-        if ((st = p.hP.ensure(3 * N * 4 + 16)) != AORESP_OK) return st;
-        if ((st = p.hQ.ensure(3 * N * 4 + 16)) != AORESP_OK) return st;
         if ((st = p.hmask.ensure(N + 16)) != AORESP_OK) return st;
         if ((st = p.P.ensure(3 * N * 4 + 16)) != AORESP_OK) return st;
         if ((st = p.Q.ensure(3 * N * 4 + 16)) != AORESP_OK) return st;
         if ((st = p.masks.ensure(N + 16)) != AORESP_OK) return st;
-        float* hp = p.hP.as<float>();
-        float* hq = p.hQ.as<float>();
+        // each request's rows go straight from its pinned block into the
+        // batch's (3, N) device arrays at its column offset
         for (int b = 0; b < nb; ++b) {
             const Request& r = *p.reqs[b];
+            if (r.n == 0) continue;
             for (int c = 0; c < 3; ++c) {
-                std::memcpy(hp + c * N + off[b], r.P.data() + c * r.n, r.n * 4);
-                std::memcpy(hq + c * N + off[b], r.Q.data() + c * r.n, r.n * 4);
+                if (hipMemcpyAsync(p.P.as<float>() + c * N + off[b], r.host + c * r.n, r.n * 4,
+                                   hipMemcpyHostToDevice, p.stream) != hipSuccess ||
+                    hipMemcpyAsync(p.Q.as<float>() + c * N + off[b], r.host + (3 + c) * r.n, r.n * 4,
+                                   hipMemcpyHostToDevice, p.stream) != hipSuccess)
+                    return AORESP_EDEVICE;
             }
         }
-        if (hipMemcpyAsync(p.P.ptr, hp, 3 * N * 4, hipMemcpyHostToDevice, p.stream) != hipSuccess) return AORESP_EDEVICE;
-        if (hipMemcpyAsync(p.Q.ptr, hq, 3 * N * 4, hipMemcpyHostToDevice, p.stream) != hipSuccess) return AORESP_EDEVICE;
         if ((st = build_plan(ctx, off.data(), nb, rps.data(), npk.data(), p.plan)) != AORESP_OK) return st;
         // the step's pipeline and result copies as one captured graph
         if ((st = launch_plan_graph(ctx, p.ws, p.plan, p.P.as<float>(), p.Q.as<float>(), p.masks.as<uint8_t>(),
@@ -293,8 +334,12 @@ aoresp_status aoresp_submit(aoresp_server* s, const float* P, const float* Q, si
     r->n = n;
     r->bytes = request_bytes(n, r->rp);
     if (r->bytes > s->cfg.hbm_budget_bytes) return AORESP_ENOMEM;
-    r->P.assign(P, P + 3 * n);
-    r->Q.assign(Q, Q + 3 * n);
+    if (n) {
+        r->host = static_cast<float*>(s->pool.get(6 * n * sizeof(float), &r->host_cls));
+        if (!r->host) return AORESP_ENOMEM;
+        std::memcpy(r->host, P, 3 * n * sizeof(float));
+        std::memcpy(r->host + 3 * n, Q, 3 * n * sizeof(float));
+    }
     r->t_submit = Clock::now();
     if (s->cfg.timeout_us) {
         r->has_deadline = true;
@@ -302,7 +347,10 @@ aoresp_status aoresp_submit(aoresp_server* s, const float* P, const float* Q, si
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stopping) return AORESP_EINVAL;
+        if (s->stopping) {
+            s->pool.put(r->host, r->host_cls);
+            return AORESP_EINVAL;
+        }
         r->id = s->next_id++;
         s->table[r->id] = r;
         s->queue.push_back(r);
@@ -370,7 +418,7 @@ void aoresp_server_destroy(aoresp_server* s) {
         p.P.release();
         p.Q.release();
         p.masks.release();
-        HostBuf* hb[] = {&p.hP, &p.hQ, &p.hmask};
+        HostBuf* hb[] = {&p.hmask};
         for (HostBuf* b : hb) {
             if (b->ptr) (void)hipHostFree(b->ptr);
             b->ptr = nullptr;
