@@ -147,6 +147,21 @@ def test_topk_parity(aor, orc):
         assert np.array_equal(masks[t], b["mask"])
 
 
+def test_topk_with_refinement_parity(aor, orc):
+    """Multi-rotation shape (three rotations, 10% inliers each, 70% outliers)
+    with a refinement grid per peak and suppression of radius 5."""
+    inst = synth.make_instance(3000, 303, n_rot=3, inlier_frac_each=0.1, sigma=0.01)
+    G, B, k, M = 128, 720, 3, 16
+    prm = aor.SolveParams(grid=G, angle_bins=B, nms_radius=5, refine_grid=M)
+    outs, masks, st = aor.est_rotations_topk(dev(inst.P), dev(inst.Q), k, prm)
+    masks = masks.cpu().numpy()
+    ors = orc.solve_topk(inst.P, inst.Q, G=G, B=B, k=k, rad=5, M=M)
+    assert len(outs) == len(ors) == 3
+    for t, (a, b) in enumerate(zip(outs, ors)):
+        assert_result_equal(a, b)
+        assert np.array_equal(masks[t], b["mask"])
+
+
 def test_enodata(aor):
     P = np.zeros((3, 1), dtype=np.float32)
     r, m, st = aor.est_rotation(P, P, aor.SolveParams(grid=64))
