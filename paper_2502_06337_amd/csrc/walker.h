@@ -52,14 +52,21 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
     return 0u;
 }
 
-// Certification threshold of the walk, T = 8e-6 (|a| + |b| + |c|).  With the
-// binary32 error bound E <= 2^-21 (|a| + |b| + |c|) (plus 2^-22 |c| for the
-// rounded W of a refinement grid), sigma*F > T puts a vertex below the curve
-// by a cross gap of at least (T - E) / (4 |d|) >= 1.7e-6, and a vertex whose
-// cross gap is at least that, on a curve of slope <= 1, is farther than
-// 1.2e-6 from it, where binary32 already gets the sign right.
+// Certification threshold of the walk, T = 5e-6 (|a| + |b| + |c|).  Let E be
+// the binary32 error bound of F at a vertex: E <= 2^-21 (|a| + |b| + |c|) on
+// the coarse lattice, plus 2^-22 |c| for the rounded W of a refinement grid.
+// (i) sigma*F > T gives an exact F > T - E; along a vertex line |dF/dy| =
+// 2 |c y + b| <= L = 2 (1.01 |c| + |b|) <= 2.84 |d| over the frame, so the
+// vertex lies below the curve by a cross gap g >= (T - E) / L.  (ii) On an
+// octant of slope <= 1 a cross gap g means a distance >= g / sqrt(2) from the
+// curve.  (iii) At distance delta from the projected circle (centre C, radius
+// R = |d| / c >= 1) |F| = c |rho - R| (rho + R) >= 2 |d| delta (1 - delta / 2R),
+// and |F| = 2 |d| delta for a line, so binary32 gets the sign of every vertex
+// farther than E / (1.99 |d|).  T must exceed E (1 + L / (1.41 * 1.99 |d|))
+// <= 2.02 E: at most 1.45e-6 (|a|+|b|+|c|) on the coarse lattice and 2.2e-6 on
+// a refinement grid, so T keeps a margin of more than 2x.
 AOR_HD __forceinline__ float cert_threshold(float a, float b, float c) {
-    return 8e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
+    return 5e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
 }
 
 // Octant pieces of the curve of (a, b, c) (c >= 0; not degenerate, not risky)
