@@ -677,7 +677,8 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_vote(const ArcRecs R, con
             const float x0 = m == 0 ? fw.U0 : fw.V0, hx = m == 0 ? fw.hx : fw.hy;
             const float y0 = m == 0 ? fw.V0 : fw.U0, hy = m == 0 ? fw.hy : fw.hx;
             if (part == 1)
-                walk_certified(aL, bL, abc.z, p >> 1, dir, abc.w, x0, hx, y0, hy, pp.x, pp.y, em, bad);
+                walk_certified(aL, bL, abc.z, p >> 1, dir, kFineCertScale * abc.w, x0, hx, y0, hy, pp.x, pp.y, em,
+                               bad);
             else
                 walk_search(aL, bL, abc.z, p >> 1, x0, hx, y0, hy, pp.x, pp.y, em, bad);
         }

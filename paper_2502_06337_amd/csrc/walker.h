@@ -52,9 +52,10 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
     return 0u;
 }
 
-// Certification threshold of the walk, T = 5e-6 (|a| + |b| + |c|).  Let E be
-// the binary32 error bound of F at a vertex: E <= 2^-21 (|a| + |b| + |c|) on
-// the coarse lattice, plus 2^-22 |c| for the rounded W of a refinement grid.
+// Certification threshold of the coarse walk, T = 3.5e-6 (|a| + |b| + |c|);
+// a refinement grid uses 1.5 T.  Let E be the binary32 error bound of F at a
+// vertex: E <= 2^-21 (|a| + |b| + |c|) on the coarse lattice, plus 2^-22 |c|
+// for the rounded W of a refinement grid.
 // (i) sigma*F > T gives an exact F > T - E; along a vertex line |dF/dy| =
 // 2 |c y + b| <= L = 2 (1.01 |c| + |b|) <= 2.84 |d| over the frame, so the
 // vertex lies below the curve by a cross gap g >= (T - E) / L.  (ii) On an
@@ -64,10 +65,11 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
 // and |F| = 2 |d| delta for a line, so binary32 gets the sign of every vertex
 // farther than E / (1.99 |d|).  T must exceed E (1 + L / (1.41 * 1.99 |d|))
 // <= 2.02 E: at most 1.45e-6 (|a|+|b|+|c|) on the coarse lattice and 2.2e-6 on
-// a refinement grid, so T keeps a margin of more than 2x.
+// a refinement grid, so both thresholds keep a margin of more than 2.3x.
 AOR_HD __forceinline__ float cert_threshold(float a, float b, float c) {
-    return 5e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
+    return 3.5e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
 }
+constexpr float kFineCertScale = 1.5f;   // refinement grids certify with 1.5 T
 
 // Octant pieces of the curve of (a, b, c) (c >= 0; not degenerate, not risky)
 // in the frame u = u0 + j*hu (j in [0, nu]), v = v0 + k*hv (k in [0, nv]).
