@@ -181,7 +181,7 @@ aoresp_status HostBuf::ensure(size_t need) {
 // items (refinement, angle histogram): 4096 correspondences.
 static constexpr int kCellChunk = 8192;
 static constexpr int kCorrChunk = 4096;
-static constexpr int kListChunk = 4096;
+static constexpr int kListChunk = 2048;
 
 int n_bucket(int64_t n) {
     int b = 0;
