@@ -67,11 +67,12 @@ AOR_HD __forceinline__ double cross_root(double a, double b, double c, double x,
     if (disc < 0.0) disc = 0.0;
     double sq = sqrt(disc);
     double qq = -(b + copysign(sq, b));
-    double r1 = qq / c;
-    double r2 = (qq != 0.0) ? K / qq : r1;
-    double lo = r1 < r2 ? r1 : r2;
-    double hi = r1 < r2 ? r2 : r1;
-    return sel ? hi : lo;
+    // qq / c and K / qq are the two roots; qq / c is the lower one when b has
+    // a positive sign bit (then qq <= 0) and the upper one otherwise, so only
+    // the requested root is divided out
+    const bool r1_wanted = (sel == 0) != (bool)signbit(b);
+    if (r1_wanted || qq == 0.0) return qq / c;
+    return K / qq;
 }
 
 AOR_HD __forceinline__ int32_t pack_range(int s, int e) {
