@@ -177,7 +177,7 @@ aoresp_status HostBuf::ensure(size_t need) {
 
 // Batch layout.  Coarse vote items: (instance, pass, band, chunk of arcs),
 // sized so that one item carries about Tuning::vote_target votes, ordered
-// largest first for the persistent work-groups.  Peak items: 64K cells.  Correspondence
+// largest first for the persistent work-groups.  Peak items: 8192 cells.  Correspondence
 // items (refinement, angle histogram): 4096 correspondences.
 static constexpr int kCellChunk = 8192;
 static constexpr int kCorrChunk = 4096;
