@@ -149,8 +149,9 @@ aoresp_status aoresp_stage_times_dev(const float* P, const float* Q, size_t n, c
 typedef struct {
     uint32_t grid;
     uint32_t n_bucket;
-    uint32_t tile_cells;  /* LDS tile of the coarse vote, cells (band width = tile_cells / grid lines) */
-    float vote_target;    /* votes per coarse work item */
+    uint32_t tile_cells;  /* LDS tile of the coarse vote, 16-bit cells, a power of two in [1024, 65536]
+                             (band width = tile_cells / grid lines, clamped to [2, grid]) */
+    float vote_target;    /* votes per coarse work item (items hold at most 64512 correspondences) */
     float vote_ms;        /* measured coarse-vote time of this choice; -1 if not measured */
 } aoresp_tuning;
 aoresp_status aoresp_autotune_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,

@@ -256,7 +256,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         int64_t chunk = (int64_t)(tu.vote_target / per_arc);
         chunk = (chunk + kVoteThreads - 1) / kVoteThreads * kVoteThreads;
         if (chunk < kVoteThreads) chunk = kVoteThreads;
-        if (chunk > (int64_t)1 << 27) chunk = (int64_t)1 << 27;   // ring entries hold the offset in 28 bits
+        if (chunk > kMaxItemArcs) chunk = kMaxItemArcs;   // 16-bit tile counters
         for (int mode = 0; mode < 2; ++mode)
             for (int band = 0; band < nbands; ++band)
                 for (int64_t i0 = 0; i0 < n; i0 += chunk) {

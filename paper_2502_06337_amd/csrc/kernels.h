@@ -19,7 +19,13 @@ constexpr uint32_t kFlagLine = 4u;        // c == 0: the projected curve is a li
 constexpr uint32_t kFlagLineDown = 8u;    // line whose cross coordinate decreases along the scan
 
 constexpr int kMaxPeaks = 8;
-constexpr int kTileCells = 32768;         // u32 cells of one coarse LDS band (128 KiB)
+// A coarse LDS band tile holds 16-bit counters, two per u32 word: the cells
+// (j, k) and (j + 1, k) of an even/odd pair of cell lines share a word.  A
+// counter takes at most one vote per correspondence of its work item, so items
+// are capped at kMaxItemArcs (< 2^16) correspondences and never overflow it.
+constexpr int kTileCells = 65536;         // 16-bit cells of one band tile (128 KiB)
+constexpr int kTileWords = kTileCells / 2 + 128;   // + padding: bw/2 pairs of G + 1 words, bw <= 256
+constexpr int kMaxItemArcs = 63 * 1024;
 constexpr int kVoteThreads = 1024;
 constexpr int kCountSlots = 64;   // partial inlier counters per result
 constexpr int kRingBody = 128;     // per-wave ring of certified parts: < 64 left over + <= 64 appended
@@ -47,7 +53,7 @@ struct Inst {
     int32_t n;            // correspondences
     int32_t G, M, w, B, rad, npk, res_off;
     float tau;
-    int32_t bw;           // coarse band width (cell lines per LDS tile), a power of two
+    int32_t bw;           // coarse band width (cell lines per LDS tile), a power of two >= 2
     int64_t grid_off;     // u32 offset of its G*G coarse grid in the grid arena
     int64_t fine_off;     // u32 offset of its npk fine grids (M*M each)
     int64_t hist_off;     // u32 offset of its npk histograms (B each)
@@ -73,13 +79,12 @@ struct PeakState {
     FineWin win;
 };
 
-// Coarse LDS band width (cell lines) for a G x G grid.
-// Band width of a coarse tile of `tile_cells` cells (at most kTileCells) for
-// a G x G grid: a power of two, at most G.
+// Band width (cell lines) of a coarse tile of `tile_cells` cells (at most
+// kTileCells) for a G x G grid: a power of two in [2, G], so lines pair up.
 __host__ __device__ inline int coarse_band_width(int G, int tile_cells = kTileCells) {
     int bw = tile_cells / G;
     if (bw > G) bw = G;
-    if (bw < 1) bw = 1;
+    if (bw < 2) bw = 2;
     return bw;
 }
 size_t coarse_lds_bytes();

@@ -74,40 +74,54 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
 // Coarse accumulator: banded LDS tiles, persistent work-groups
 // --------------------------------------------------------------------------
 
-// Cells of a band tile, stored along-line major: cell (along jl, cross k) at
-// jl * S + k with S = G + 1, so the lanes of a wave (different curves, mostly
-// on the same line) hit spread-out banks, and the column pass's flush, which
-// reads across lines, is conflict-free too.  Cells outside the disk are
-// counted here and dropped at the flush, so the walk only clips to the frame
-// (and, in the row pass, to the columns its quarter owns).
+// Cells of a band tile: 16-bit counters, the cells (j, k) and (j + 1, k) of
+// an even/odd line pair in the low and high half of one word, word rows of
+// Sw = G + 1 words per line pair (pair m, cross k at m * Sw + k).  The lanes
+// of a wave (different curves, mostly on the same line) hit spread-out banks,
+// and the column pass's flush, which reads across lines, is conflict-free too.
+// Cells outside the disk are counted here and dropped at the flush, so the
+// walk only clips to the frame (and, in the row pass, to the columns its
+// quarter owns).
 struct CoarseEmit {
     uint32_t* tile;
-    int jofs, lg;          // S = 2^lg + 1, jofs = -band0 * S
+    int jofs, lg;          // Sw = 2^lg + 1, jofs = -(band0 / 2) * Sw
     int clo, chi;          // allowed cross indices (callers skip a walk when chi < clo)
     uint32_t* sink;        // this lane's word of a scratch row that is never flushed
     int qa = 0, qb = 0;    // clean-state cell offsets relative to clo
-    __device__ __forceinline__ uint32_t* line_of(int j) const { return tile + (((j << lg) + j) + jofs); }
+    struct Cursor {
+        uint32_t* p;       // word row of the line, shifted by clo
+        uint32_t inc;      // 1 on an even line, 1 << 16 on an odd one
+    };
+    __device__ __forceinline__ uint32_t* row_of(int j) const {
+        const int m = j >> 1;
+        return tile + (((m << lg) + m) + jofs);
+    }
+    __device__ __forceinline__ static uint32_t inc_of(int j) { return 1u << ((j & 1) << 4); }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
-        uint32_t* line = line_of(j);
+        uint32_t* row = row_of(j);
+        const uint32_t inc = inc_of(j);
         klo = max(klo, clo);
         khi = min(khi, chi);
 #pragma unroll 1
-        for (int k = klo; k <= khi; ++k) atomicAdd(line + k, 1u);
+        for (int k = klo; k <= khi; ++k) atomicAdd(row + k, inc);
     }
-    // cursor: line base shifted by clo
-    __device__ __forceinline__ uint32_t* start(int j, int off) {
+    __device__ __forceinline__ Cursor start(int j, int off) {
         qa = off - 1 - clo;
         qb = -off - clo;
-        return line_of(j) + clo;
+        return Cursor{row_of(j) + clo, inc_of(j)};
     }
-    __device__ __forceinline__ uint32_t* next(uint32_t* c) const { return c + ((1 << lg) + 1); }
+    // the next line: the other half of the same word row after an even line,
+    // the low half of the next word row after an odd one
+    __device__ __forceinline__ Cursor next(Cursor c) const {
+        return Cursor{c.p + (c.inc >> 16) * ((1 << lg) + 1), c.inc ^ 0x10001u};
+    }
     // cells r - 1 + off and, if second, r - off; a cell outside the allowed
     // range goes to the lane's sink word instead (no divergent branch)
-    __device__ __forceinline__ void pair(uint32_t* c, int r, bool second) const {
+    __device__ __forceinline__ void pair(Cursor c, int r, bool second) const {
         const unsigned span = (unsigned)(chi - clo);
         const int a = r + qa, b = r + qb;
-        atomicAdd((unsigned)a <= span ? c + a : sink, 1u);
-        atomicAdd(second && (unsigned)b <= span ? c + b : sink, 1u);
+        atomicAdd((unsigned)a <= span ? c.p + a : sink, c.inc);
+        atomicAdd(second && (unsigned)b <= span ? c.p + b : sink, c.inc);
     }
 };
 
@@ -130,9 +144,9 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     uint32_t* tile = smem;
-    uint32_t* rbody = smem + kTileCells + 128 + wid * (kRingBody + kRingLine);
+    uint32_t* rbody = smem + kTileWords + wid * (kRingBody + kRingLine);
     uint32_t* rline = rbody + kRingBody;
-    uint32_t* sinkrow = smem + kTileCells + 128 + kWaves * (kRingBody + kRingLine);   // 64 words, never read
+    uint32_t* sinkrow = smem + kTileWords + kWaves * (kRingBody + kRingLine);   // 64 words, never read
     int16_t* dlim = reinterpret_cast<int16_t*>(sinkrow + 64);
     const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t bad = 0;
@@ -153,11 +167,11 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         const int bw = I.bw;
         const int band0 = band * bw;
         const int bwb = (band0 + bw <= G) ? bw : (G - band0);
-        const int S = G + 1;                 // tile line stride
-        const int tile_cells = bwb * S;
+        const int Sw = G + 1;                // words per line pair
+        const int tile_words = (bwb >> 1) * Sw;
         const int lbw = 31 - __clz(bwb), lg = 31 - __clz(G);   // both powers of two
         const float h = 2.0f / (float)G;
-        for (int t = tid; t < tile_cells; t += kVoteThreads) tile[t] = 0u;
+        for (int t = tid; t < tile_words; t += kVoteThreads) tile[t] = 0u;
         for (int t = tid; t < bwb; t += kVoteThreads) {
             dlim[2 * t] = I.disk[2 * (band0 + t)];
             dlim[2 * t + 1] = I.disk[2 * (band0 + t) + 1];
@@ -200,7 +214,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     octant_walk_info(mode, p, geo2, dir, slo, shi);
                     const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
                     const int sel = p >> 1;
-                    CoarseEmit em{tile, -band0 * S, lg, 0, G - 1, sinkrow + lane};
+                    CoarseEmit em{tile, -(band0 >> 1) * Sw, lg, 0, G - 1, sinkrow + lane};
                     float aL = abc.x, bL = abc.y;
                     if (mode == 1) {
                         int ja, jb;
@@ -262,7 +276,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                         float f3 = vertex_F(abc.y, abc.z, uu1, au1, v1);
                         bool le = (f0 <= 0.0f) | (f1 <= 0.0f) | (f2 <= 0.0f) | (f3 <= 0.0f);
                         bool ge = (f0 >= 0.0f) | (f1 >= 0.0f) | (f2 >= 0.0f) | (f3 >= 0.0f);
-                        if (le && ge) atomicAdd(&tile[jl * S + k], 1u);
+                        if (le && ge) atomicAdd(&tile[(jl >> 1) * Sw + k], 1u << ((jl & 1) << 4));
                     }
                 }
                 bool any = false;
@@ -312,23 +326,30 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         }
         __syncthreads();
         // flush the band's cells that meet the disk into this instance's
-        // accumulator; consecutive threads take consecutive grid cells
+        // accumulator; consecutive threads take consecutive words (line pairs
+        // of one cross index in the column pass, cross indices of one line
+        // pair in the row pass)
         uint32_t* grid = grid_arena + I.grid_off;
-        for (int t = tid; t < bwb * G; t += kVoteThreads) {
-            int jl, k;
-            size_t gi;
+        const int lhb = lbw - 1;
+        for (int t = tid; t < (bwb >> 1) * G; t += kVoteThreads) {
+            int m, k;
+            size_t g0, g1;
             if (mode == 0) {
-                k = t >> lbw;
-                jl = t & (bwb - 1);
-                gi = (size_t)k * G + band0 + jl;
+                k = t >> lhb;
+                m = t & ((bwb >> 1) - 1);
+                g0 = (size_t)k * G + band0 + 2 * m;
+                g1 = g0 + 1;
             } else {
-                jl = t >> lg;
+                m = t >> lg;
                 k = t & (G - 1);
-                gi = (size_t)(band0 + jl) * G + k;
+                g0 = (size_t)(band0 + 2 * m) * G + k;
+                g1 = g0 + G;
             }
-            const uint32_t v = tile[jl * S + k];
-            if (!v || k < dlim[2 * jl] || k > dlim[2 * jl + 1]) continue;
-            atomicAdd(&grid[gi], v);
+            const uint32_t w = tile[m * Sw + k];
+            if (!w) continue;
+            const uint32_t v0 = w & 0xFFFFu, v1 = w >> 16;
+            if (v0 && k >= dlim[4 * m] && k <= dlim[4 * m + 1]) atomicAdd(&grid[g0], v0);
+            if (v1 && k >= dlim[4 * m + 2] && k <= dlim[4 * m + 3]) atomicAdd(&grid[g1], v1);
         }
         __syncthreads();
     }
@@ -1002,10 +1023,9 @@ __global__ void k_zero_u32(uint32_t* p, size_t count) {
 // --------------------------------------------------------------------------
 
 size_t coarse_lds_bytes() {
-    // tile (bw lines of G + 1 cells, bw <= 128 beyond kTileCells) + per-wave
-    // rings (u32) + sink row + in-disk limits (2 x int16 per band line, <= 256 lines)
-    return (size_t)(kTileCells + 128) * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 64 * 4 +
-           2 * 2 * 256;
+    // tile (bw / 2 line pairs of G + 1 words, bw <= 256) + per-wave rings
+    // (u32) + sink row + in-disk limits (2 x int16 per band line, <= 256 lines)
+    return (size_t)kTileWords * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 64 * 4 + 2 * 2 * 256;
 }
 
 static void set_lds_limit(const void* fn) {

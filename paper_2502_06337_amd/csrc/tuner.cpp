@@ -18,7 +18,7 @@ using namespace aoresp;
 
 namespace {
 
-const int kTiles[] = {8192, 16384, 32768};
+const int kTiles[] = {16384, 32768, 65536};
 const double kTargets[] = {0.75e6, 1.5e6, 3.0e6, 6.0e6};
 
 // Coarse-vote time (ms) of one solve of (P, Q) with the work split forced.

@@ -33,7 +33,7 @@ def test_tuned_solve_is_bit_identical(aor, tmp_path):
     g0 = aor.coarse_grid(P, Q, 512).cpu().numpy()
     chosen = aor.autotune(P, Q, prm)
     assert chosen["grid"] == 512 and chosen["vote_ms"] > 0
-    assert chosen["tile_cells"] in (8192, 16384, 32768)
+    assert chosen["tile_cells"] in (16384, 32768, 65536)
     assert aor.tuner_get(512, 60000) == chosen
     r1, m1, s1 = aor.est_rotation(P, Q, prm)
     g1 = aor.coarse_grid(P, Q, 512).cpu().numpy()
@@ -48,7 +48,7 @@ def test_tuned_solve_is_bit_identical(aor, tmp_path):
     aor.tuner_save(path)
     text = open(path).read()
     assert '"grid": 512' in text
-    for tile in (8192, 16384, 32768):
+    for tile in (16384, 32768, 65536):
         for target in (7.5e5, 6e6):
             line = text.splitlines()[0]
             import json
