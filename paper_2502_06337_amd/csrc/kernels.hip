@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
 // quarter owns).
 struct CoarseEmit {
     uint32_t* tile;
-    int jofs, lg;          // Sw = 2^lg + 1, jofs = -(band0 / 2) * Sw
+    int jofs, sw;          // sw = G + 1 words per line pair, jofs = -(band0 / 2) * sw
     int clo, chi;          // allowed cross indices (callers skip a walk when chi < clo)
     uint32_t* sink;        // this lane's word of a scratch row that is never flushed
     int qa = 0, qb = 0;    // clean-state cell offsets relative to clo
@@ -92,10 +92,7 @@ struct CoarseEmit {
         uint32_t* p;       // word row of the line, shifted by clo
         uint32_t inc;      // 1 on an even line, 1 << 16 on an odd one
     };
-    __device__ __forceinline__ uint32_t* row_of(int j) const {
-        const int m = j >> 1;
-        return tile + (((m << lg) + m) + jofs);
-    }
+    __device__ __forceinline__ uint32_t* row_of(int j) const { return tile + ((int)__umul24(j >> 1, sw) + jofs); }
     __device__ __forceinline__ static uint32_t inc_of(int j) { return 1u << ((j & 1) << 4); }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
         uint32_t* row = row_of(j);
@@ -113,7 +110,7 @@ struct CoarseEmit {
     // the next line: the other half of the same word row after an even line,
     // the low half of the next word row after an odd one
     __device__ __forceinline__ Cursor next(Cursor c) const {
-        return Cursor{c.p + (c.inc >> 16) * ((1 << lg) + 1), c.inc ^ 0x10001u};
+        return Cursor{c.p + __umul24(c.inc >> 16, sw), c.inc ^ 0x10001u};
     }
     // cells r - 1 + off and, if second, r - off; a cell outside the allowed
     // range goes to the lane's sink word instead (no divergent branch)
@@ -214,7 +211,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     octant_walk_info(mode, p, geo2, dir, slo, shi);
                     const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
                     const int sel = p >> 1;
-                    CoarseEmit em{tile, -(band0 >> 1) * Sw, lg, 0, G - 1, sinkrow + lane};
+                    CoarseEmit em{tile, -(band0 >> 1) * Sw, Sw, 0, G - 1, sinkrow + lane};
                     float aL = abc.x, bL = abc.y;
                     if (mode == 1) {
                         int ja, jb;

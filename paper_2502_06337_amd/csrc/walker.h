@@ -375,11 +375,18 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
     bool clean = cb && ca && hi == lo - 1;
     int r = lo - off;   // the row evaluated next while clean
     float yr = y0 + (float)r * hy;
-    const float dy_up = (float)(1 - off) * hy, dy_dn = -(float)off * hy;   // exact: off is 0 or 1
+    float dy_up = (float)(1 - off) * hy, dy_dn = -(float)off * hy;   // exact: off is 0 or 1
+#if defined(__HIP_DEVICE_COMPILE__)
+    // opaque to the optimiser, so that the row update below stays one select
+    // of these two values instead of a select of 1 - off / -off times hy
+    __asm__("" : "+v"(dy_up), "+v"(dy_dn));
+#endif
     auto cur = emit.start(cs, off);
-    // fresh: the clean state was left on the previous line (|F| <= T there);
-    // lo, hi, cb and ca are rebuilt from r and that value, lastf
-    bool fresh = false;
+    // lastf: the value evaluated on the previous line if that line took the
+    // clean step, else 0.  A lane that is no longer clean and has lastf != 0
+    // left the clean state there (|F| <= T): lo, hi, cb and ca are rebuilt
+    // from r and lastf.  (A lane still clean that meets a zero vertex rebuilds
+    // its state from r alone, overriding that.)
     float lastf = 0.0f;
     for (int j = cs; j < ce; ++j, cur = emit.next(cur)) {
         x += hx;
@@ -393,17 +400,16 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             r += (up ? 1 : 0) - off;
             if (kLattice) yr += up ? dy_up : dy_dn;
             clean = fabsf(f) > T;
-            fresh = !clean;
             lastf = f;
             continue;
         }
-        if (fresh) {
+        if (lastf != 0.0f) {
             // the evaluated vertex of the previous line was not certified
             lo = r + off;
             hi = lo - 1;
             cb = !(lastf > 0.0f);
             ca = !(lastf < 0.0f);
-            fresh = false;
+            lastf = 0.0f;
         }
         if (clean) {
             // zero vertex on the evaluated row: rebuild the full state
