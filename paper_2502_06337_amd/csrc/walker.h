@@ -53,23 +53,24 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
 }
 
 // Certification threshold of the coarse walk, T = 2e-6 (|a| + |b| + |c|); a
-// refinement grid uses 1.5 T.  Let E bound the binary32 error of F at a vertex
-// with sigma*F > T.  On the coarse lattice W is exact, and the three products,
-// the inner sum and the outer sum give E <= 2^-24 (1.26 |c| + 4.25 (|a| + |b|))
-// <= 2^-21 (|a| + |b| + |c|) (frame margin of two lines included, any G >= 64);
-// a refinement grid rounds W as well, adding 2^-22 |c|.
+// refinement grid uses 1.5 T.  Evaluated vertices have |u| <= 1 and |v| <=
+// 1 + 4h <= 1.125 (the crossing stays within the frame plus the clip margin).
+// Let E bound the binary32 error of F at a vertex with sigma*F > T.  On the
+// coarse lattice W is exact, and the three products, the inner sum and the
+// outer sum give E <= 2^-24 (1.27 |c| + 4.5 (|a| + |b|)) <= 2^-21 (|a| + |b| +
+// |c|); a refinement grid rounds W as well, adding 2^-22 |c|.
 // (i) sigma*F > T gives an exact F > T - E; along a vertex line |dF/dy| =
-// 2 |c y + b| <= L = 2 (1.07 |c| + |b|) <= 2.93 |d| over the frame, so the
-// vertex lies beyond the curve by a cross gap g >= (T - E) / L.  (ii) The gap
-// carries over to the row of the next line that the certificate speaks for,
-// and on an octant of slope <= 1 a cross gap g means a distance >= g / sqrt(2)
-// from the curve.  (iii) At distance delta from the projected circle (centre C,
-// radius R = |d| / c >= 1) |F| = c |rho - R| (rho + R) >= 2 |d| delta
-// (1 - delta / 2R), and |F| = 2 |d| delta for a line, so binary32 gets the sign
-// of every vertex farther than E / (1.99 |d|).  T must therefore exceed
-// E (1 + sqrt(2) L / (1.99 |d|)) <= 3.09 E: 1.48e-6 (|a| + |b| + |c|) on the
-// coarse lattice and 2.2e-6 on a refinement grid, so both thresholds keep a
-// margin of 1.35x on these bounds (2.5x on the coarse lattice's own 4.25 term).
+// 2 |c y + b| <= L = 2 (1.125 |c| + |b|) <= 3.01 |d|, so the vertex lies
+// beyond the curve by a cross gap g >= (T - E) / L.  (ii) The gap carries over
+// to the row of the next line that the certificate speaks for, and on an
+// octant of slope <= 1 a cross gap g means a distance >= g / sqrt(2) from the
+// curve.  (iii) At distance delta from the projected circle (centre C, radius
+// R = |d| / c >= 1) |F| = c |rho - R| (rho + R) >= 2 |d| delta (1 - delta / 2R),
+// and |F| = 2 |d| delta for a line, so binary32 gets the sign of every vertex
+// farther than E / (1.99 |d|).  T must therefore exceed
+// E (1 + sqrt(2) L / (1.99 |d|)) <= 3.14 E: 1.5e-6 (|a| + |b| + |c|) on the
+// coarse lattice and 2.25e-6 on a refinement grid, a margin of 1.33x for both
+// thresholds (2.4x on the coarse lattice's own 4.5 term).
 AOR_HD __forceinline__ float cert_threshold(float a, float b, float c) {
     return 2.0e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
 }
