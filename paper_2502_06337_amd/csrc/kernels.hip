@@ -83,6 +83,7 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
 // walk only clips to the frame (and, in the row pass, to the columns its
 // quarter owns).
 struct CoarseEmit {
+    static constexpr bool kAudit = false;
     uint32_t* tile;
     int jofs, sw;          // sw = G + 1 words per line pair, jofs = -(band0 / 2) * sw
     int clo, chi;          // allowed cross indices (callers skip a walk when chi < clo)
@@ -480,6 +481,7 @@ __global__ void k_peak_finish(const Inst* __restrict__ insts, int ninst, const u
 // --------------------------------------------------------------------------
 
 struct FineEmit {
+    static constexpr bool kAudit = false;
     uint32_t* tile;
     int mode, M;
     float U0, V0, hx, hy;

@@ -353,7 +353,9 @@ AOR_HD __forceinline__ void walk_search(float aL, float bL, float c, int sel, fl
 // Emitter interface: start(j, off) returns a cursor for line j (and may set
 // up the pair offsets for this octant), next(cursor) advances it by a line,
 // pair(cursor, r, second) emits the clean-state cells, and emit(j, klo, khi)
-// a general range.  kLattice: every vertex coordinate y0 + k*hy is exact and
+// a general range.  An emitter with kAudit set also receives, on every clean
+// line, the values at the two rows next to the evaluated one (audit(fb, fa)),
+// so that a host test can check what the certificates claim.  kLattice: every vertex coordinate y0 + k*hy is exact and
 // so are sums of them (the coarse grid), so the evaluated row's coordinate is
 // carried from line to line instead of recomputed.
 template <bool kLattice = false, class Emit>
@@ -400,6 +402,12 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         // evaluated on every lane; only clean lanes use it
         const float f = vertex_F(sb, sc, xx, ax, kLattice ? yr : y0 + (float)r * hy);
         if (clean && f != 0.0f) {
+            if constexpr (Emit::kAudit) {
+                // test builds only: the certificates vouch for sigma*F > 0 at
+                // row r - 1 and sigma*F < 0 at row r + 1 of this line
+                emit.audit(vertex_F(sb, sc, xx, ax, y0 + (float)(r - 1) * hy),
+                           vertex_F(sb, sc, xx, ax, y0 + (float)(r + 1) * hy));
+            }
             const bool up = f > 0.0f;
             emit.pair(cur, r, up != (off != 0));
             r += (up ? 1 : 0) - off;
