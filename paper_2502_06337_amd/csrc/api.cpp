@@ -178,9 +178,9 @@ aoresp_status HostBuf::ensure(size_t need) {
 // Batch layout.  Coarse vote items: (instance, pass, band, chunk of arcs),
 // sized so that one item carries about Tuning::vote_target votes, ordered
 // largest first for the persistent work-groups.  Peak items: 8192 cells.  Correspondence
-// items (refinement, angle histogram): 4096 correspondences.
+// items (angle histogram): 2048 correspondences; refinement list items: 2048.
 static constexpr int kCellChunk = 8192;
-static constexpr int kCorrChunk = 4096;
+static constexpr int kCorrChunk = 2048;
 static constexpr int kListChunk = 2048;
 
 int n_bucket(int64_t n) {

@@ -939,60 +939,66 @@ __global__ __launch_bounds__(1024) void k_angle_peak(const uint32_t* __restrict_
 // that no single address takes one atomic per block; k_inliers_total sums
 // the partials into the result.  Blocks that straddle two instances add per
 // correspondence straight into the result.
+// One block per kInlierSub x 256 consecutive columns: the columns' inputs
+// are loaded first, then each is tested against every peak of its instance.
+constexpr int kInlierSub = 4;
 __global__ __launch_bounds__(256) void k_inliers(const float* __restrict__ P, const float* __restrict__ Q,
                                                  int64_t N, const Inst* __restrict__ insts, int ninst,
                                                  const PeakState* st, aoresp_result* res,
                                                  uint8_t* __restrict__ masks, uint32_t* __restrict__ partial) {
     __shared__ uint32_t cnt[kMaxPeaks];
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t first = (int64_t)blockIdx.x * blockDim.x;
-    const int64_t last = min(first + (int64_t)blockDim.x, N) - 1;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x * kInlierSub;
+    const int64_t last = min(first + (int64_t)blockDim.x * kInlierSub, N) - 1;
     const int bfirst = find_inst(insts, ninst, first);
     const bool block_uniform = find_inst(insts, ninst, last) == bfirst;
     if (threadIdx.x < kMaxPeaks) cnt[threadIdx.x] = 0u;
     __syncthreads();
-    const bool live = i < N;
-    const int b = live ? (block_uniform ? bfirst : find_inst(insts, ninst, i)) : bfirst;
-    const Inst& I = insts[b];
-    float p0 = 0, p1 = 0, p2 = 0, q0 = 0, q1 = 0, q2 = 0;
-    if (live) {
-        p0 = P[i];
-        p1 = P[N + i];
-        p2 = P[2 * N + i];
-        q0 = Q[i];
-        q1 = Q[N + i];
-        q2 = Q[2 * N + i];
-    }
-    const float tt = I.tau * I.tau;
-    const int npk = insts[bfirst].npk;
-    for (int t = 0; t < kMaxPeaks; ++t) {
-        if (block_uniform && t >= npk) break;
-        bool act = live && t < I.npk;
-        if (!block_uniform && !__any(act)) break;
-        uint8_t m = 0;
-        if (act && I.n >= 2 && st[I.res_off + t].valid) {
-            const float* R = res[I.res_off + t].R;
-            float e[3];
-            float qv[3] = {q0, q1, q2};
-            for (int j = 0; j < 3; ++j) {
-                float t0 = R[j * 3 + 0] * p0;
-                float t1 = R[j * 3 + 1] * p1;
-                float t2 = R[j * 3 + 2] * p2;
-                float sm = (t0 + t1) + t2;
-                e[j] = sm - qv[j];
-            }
-            float e0 = e[0] * e[0];
-            float e1 = e[1] * e[1];
-            float e2 = e[2] * e[2];
-            float res2 = (e0 + e1) + e2;
-            m = res2 <= tt ? 1 : 0;
+    float pv[kInlierSub][3], qv[kInlierSub][3];
+#pragma unroll
+    for (int u = 0; u < kInlierSub; ++u) {
+        const int64_t i = first + (int64_t)u * blockDim.x + threadIdx.x;
+        const bool live = i < N;
+        for (int k = 0; k < 3; ++k) {
+            pv[u][k] = live ? P[k * N + i] : 0.0f;
+            qv[u][k] = live ? Q[k * N + i] : 0.0f;
         }
-        if (act && masks) masks[(size_t)t * N + i] = m;
-        if (block_uniform) {
-            unsigned long long bal = __ballot(m != 0);
-            if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&cnt[t], (uint32_t)__popcll(bal));
-        } else if (m) {
-            atomicAdd(&res[I.res_off + t].n_inliers, 1u);
+    }
+    const int npk = insts[bfirst].npk;
+#pragma unroll
+    for (int u = 0; u < kInlierSub; ++u) {
+        const int64_t i = first + (int64_t)u * blockDim.x + threadIdx.x;
+        const bool live = i < N;
+        const int b = live ? (block_uniform ? bfirst : find_inst(insts, ninst, i)) : bfirst;
+        const Inst& I = insts[b];
+        const float tt = I.tau * I.tau;
+        for (int t = 0; t < kMaxPeaks; ++t) {
+            if (block_uniform && t >= npk) break;
+            bool act = live && t < I.npk;
+            if (!block_uniform && !__any(act)) break;
+            uint8_t m = 0;
+            if (act && I.n >= 2 && st[I.res_off + t].valid) {
+                const float* R = res[I.res_off + t].R;
+                float e[3];
+                for (int j = 0; j < 3; ++j) {
+                    float t0 = R[j * 3 + 0] * pv[u][0];
+                    float t1 = R[j * 3 + 1] * pv[u][1];
+                    float t2 = R[j * 3 + 2] * pv[u][2];
+                    float sm = (t0 + t1) + t2;
+                    e[j] = sm - qv[u][j];
+                }
+                float e0 = e[0] * e[0];
+                float e1 = e[1] * e[1];
+                float e2 = e[2] * e[2];
+                float res2 = (e0 + e1) + e2;
+                m = res2 <= tt ? 1 : 0;
+            }
+            if (act && masks) masks[(size_t)t * N + i] = m;
+            if (block_uniform) {
+                unsigned long long bal = __ballot(m != 0);
+                if ((threadIdx.x & 63) == 0 && bal) atomicAdd(&cnt[t], (uint32_t)__popcll(bal));
+            } else if (m) {
+                atomicAdd(&res[I.res_off + t].n_inliers, 1u);
+            }
         }
     }
     if (block_uniform) {
@@ -1102,8 +1108,9 @@ void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts
                     aoresp_result* res, int nres, uint8_t* masks, uint32_t* partial, hipStream_t s) {
     if (N <= 0) return;
     launch_zero_u32(partial, (size_t)nres * kCountSlots, s);
-    hipLaunchKernelGGL(k_inliers, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, Q, N, insts, ninst, st, res,
-                       masks, partial);
+    const int64_t per_block = 256 * kInlierSub;
+    hipLaunchKernelGGL(k_inliers, dim3((unsigned)((N + per_block - 1) / per_block)), dim3(256), 0, s, P, Q, N, insts,
+                       ninst, st, res, masks, partial);
     hipLaunchKernelGGL(k_inliers_total, dim3((unsigned)((nres + 63) / 64)), dim3(64), 0, s, partial, nres, res);
 }
 
