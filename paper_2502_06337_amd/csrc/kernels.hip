@@ -62,7 +62,7 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
         colp.x = kRiskyMark;
     } else if (!(fl & kFlagDegenerate)) {
         double h = 2.0 / G;
-        circle_pieces(a, b, c, fl, -1.0, h, G, -1.0, h, G, 2.0 * h, colp, rowp, geo);
+        circle_pieces<true>(a, b, c, fl, -1.0, h, G, -1.0, h, G, 2.0 * h, colp, rowp, geo);
     }
     R.abc[i] = make_float4(a, b, c, cert_threshold(a, b, c));
     R.colp[i] = colp;
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(kFineThreads) void k_fine_vote(const ArcRecs R, con
                 continue;
             }
             int4 colp, rowp, geo;
-            circle_pieces(abc.x, abc.y, abc.z, fl, fw.U0, fw.hx, M, fw.V0, fw.hy, M, g.margin, colp, rowp, geo);
+            circle_pieces<false>(abc.x, abc.y, abc.z, fl, fw.U0, fw.hx, M, fw.V0, fw.hy, M, g.margin, colp, rowp, geo);
             cabc[c] = abc;
             ccol[c] = colp;
             crow[c] = rowp;

@@ -18,9 +18,19 @@ AOR_HD __forceinline__ int clamp_index(double t, int lo, int hi) {
     return (int)t;
 }
 
+// Index of coordinate t on the lattice x0 + k * hx, before rounding: (t - x0)
+// / hx, computed as a product with 1 / hx when the step is a power of two
+// (then both give the same value).
+template <bool kPow2Step>
+AOR_HD __forceinline__ double lattice_index(double t, double x0, double hx) {
+    if (kPow2Step) return (t - x0) * (1.0 / hx);
+    return (t - x0) / hx;
+}
+
 // Restrict a monotone octant [s, e] (vertex indices along x) to the vertex
 // lines where its crossing lies in [ylo, yhi].  side selects the along-root
 // (0: smaller, 1: larger) when solving for x at a given cross value.
+template <bool kPow2Step>
 AOR_HD inline void clip_octant(double aL, double bL, double c, int sel, int side, double x0, double hx, double ylo,
                                double yhi, int nmax, int& s, int& e) {
     if (s >= e) return;
@@ -36,8 +46,8 @@ AOR_HD inline void clip_octant(double aL, double bL, double c, int sel, int side
         if (ys > yhi) xa = cross_root(bL, aL, c, yhi, side);
         if (ye < ylo) xb = cross_root(bL, aL, c, ylo, side);
     }
-    int sa = clamp_index(floor((xa - x0) / hx) - 1.0, -2, nmax + 2);
-    int eb = clamp_index(ceil((xb - x0) / hx) + 1.0, -2, nmax + 2);
+    int sa = clamp_index(floor(lattice_index<kPow2Step>(xa, x0, hx)) - 1.0, -2, nmax + 2);
+    int eb = clamp_index(ceil(lattice_index<kPow2Step>(xb, x0, hx)) + 1.0, -2, nmax + 2);
     if (sa > s) s = sa;
     if (eb < e) e = eb;
     if (e < s) e = s;
@@ -93,7 +103,10 @@ constexpr float kFineCertScale = 1.5f;   // refinement grids certify with 1.5 T
 // [ja, jb); row pieces own rows [ka - 3, kb + 3) but only columns < ja (lower
 // u-root) or >= jb (upper u-root); the 3 extra rows cover the cells around the
 // 45-degree points.  geo = (ja | jb << 16, jm | km << 16, ka | kb << 16, flags)
-// with jm, km the lines just before the extreme points.
+// with jm, km the lines just before the extreme points.  kCoarse: the frame
+// is the coarse lattice (hu = hv, a power of two), so divisions by the step
+// are products and the slope ratio rho is 1.
+template <bool kCoarse>
 AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, double u0, double hu, int nu,
                                  double v0, double hv, int nv, double margin, int4& colp, int4& rowp, int4& geo) {
     const int E = pack_range(0, 0);
@@ -110,7 +123,7 @@ AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, d
         if (fabs(a) * hu <= fabs(b) * hv) {
             s = 0;
             e = nu;
-            clip_octant(a, b, 0.0, 0, 0, u0, hu, vlo, vhi, nu, s, e);
+            clip_octant<kCoarse>(a, b, 0.0, 0, 0, u0, hu, vlo, vhi, nu, s, e);
             if (s < 0) s = 0;
             if (e > nu) e = nu;
             int32_t pr = pack_range(s, e > s ? e : s);
@@ -120,7 +133,7 @@ AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, d
         } else {
             s = 0;
             e = nv;
-            clip_octant(b, a, 0.0, 0, 0, v0, hv, ulo, uhi, nv, s, e);
+            clip_octant<kCoarse>(b, a, 0.0, 0, 0, v0, hv, ulo, uhi, nv, s, e);
             if (s < 0) s = 0;
             if (e > nv) e = nv;
             int32_t pr = pack_range(s, e > s ? e : s);
@@ -137,26 +150,27 @@ AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, d
     // rho = hv/hu the column band is |u - cu| <= r rho / sqrt(1 + rho^2) and
     // the row band |v - cv| <= r / sqrt(1 + rho^2) (r / sqrt(2) each on a
     // square grid).
-    double rho = hv / hu;
-    double qn = 1.0 / sqrt(1.0 + rho * rho);
+    // on the coarse lattice rho = 1 and qn folds to a constant
+    const double rho = kCoarse ? 1.0 : hv / hu;
+    const double qn = 1.0 / sqrt(1.0 + rho * rho);
     double qu = r * rho * qn, qv = r * qn;
     // Indices are clamped 8 lines outside the frame so that the 3-line
     // extension of a clamped band never reaches into the frame.
     int lim_u = nu + 8, lim_v = nv + 8;
-    int ja = clamp_index(ceil((cu - qu - u0) / hu), -8, lim_u);
-    int jb = clamp_index(floor((cu + qu - u0) / hu), -8, lim_u);
-    int ka = clamp_index(ceil((cv - qv - v0) / hv), -8, lim_v);
-    int kb = clamp_index(floor((cv + qv - v0) / hv), -8, lim_v);
+    int ja = clamp_index(ceil(lattice_index<kCoarse>(cu - qu, u0, hu)), -8, lim_u);
+    int jb = clamp_index(floor(lattice_index<kCoarse>(cu + qu, u0, hu)), -8, lim_u);
+    int ka = clamp_index(ceil(lattice_index<kCoarse>(cv - qv, v0, hv)), -8, lim_v);
+    int kb = clamp_index(floor(lattice_index<kCoarse>(cv + qv, v0, hv)), -8, lim_v);
     if (jb < ja) jb = ja;
     if (kb < ka) kb = ka;
-    int jm = clamp_index(floor((cu - u0) / hu), ja, jb);
-    int km = clamp_index(floor((cv - v0) / hv), ka, kb);
+    int jm = clamp_index(floor(lattice_index<kCoarse>(cu, u0, hu)), ja, jb);
+    int km = clamp_index(floor(lattice_index<kCoarse>(cv, v0, hv)), ka, kb);
     int cs[4] = {ja, jm, ja, jm}, ce[4] = {jm, jb, jm, jb};
     int32_t cp[4];
     for (int p = 0; p < 4; ++p) {
         s = cs[p] < 0 ? 0 : cs[p];
         e = ce[p] > nu ? nu : ce[p];
-        if (s < e) clip_octant(a, b, c, p >> 1, p & 1, u0, hu, vlo, vhi, nu, s, e);
+        if (s < e) clip_octant<kCoarse>(a, b, c, p >> 1, p & 1, u0, hu, vlo, vhi, nu, s, e);
         if (s < 0) s = 0;
         if (e > nu) e = nu;
         cp[p] = pack_range(s, e > s ? e : s);
@@ -167,7 +181,7 @@ AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, d
     for (int p = 0; p < 4; ++p) {
         s = rs[p] < 0 ? 0 : rs[p];
         e = re[p] > nv ? nv : re[p];
-        if (s < e) clip_octant(b, a, c, p >> 1, p & 1, v0, hv, ulo, uhi, nv, s, e);
+        if (s < e) clip_octant<kCoarse>(b, a, c, p >> 1, p & 1, v0, hv, ulo, uhi, nv, s, e);
         if (s < 0) s = 0;
         if (e > nv) e = nv;
         rp[p] = pack_range(s, e > s ? e : s);

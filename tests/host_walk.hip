@@ -163,7 +163,7 @@ int hw_coarse_grid(const float* P, const float* Q, long n, int G, uint32_t* grid
         }
         int4 colp, rowp, geo;
         const double hd = 2.0 / G;
-        circle_pieces(a, b, c, fl, -1.0, hd, G, -1.0, hd, G, 2.0 * hd, colp, rowp, geo);
+        circle_pieces<true>(a, b, c, fl, -1.0, hd, G, -1.0, hd, G, 2.0 * hd, colp, rowp, geo);
         const int32_t ranges[2][4] = {{colp.x, colp.y, colp.z, colp.w}, {rowp.x, rowp.y, rowp.z, rowp.w}};
         int ja, jb;
         unpack_range(geo.x, ja, jb);
@@ -214,7 +214,7 @@ int hw_fine_grid(const float* P, const float* Q, long n, float U0, float V0, flo
         const uint32_t fl = displacement(P, Q, n, i, a, b, c);
         if (fl & (kFlagDegenerate | kFlagRisky)) continue;
         int4 colp, rowp, geo;
-        circle_pieces(a, b, c, fl, U0, hx, M, V0, hy, M, 2.0 * (double)(hx > hy ? hx : hy), colp, rowp, geo);
+        circle_pieces<false>(a, b, c, fl, U0, hx, M, V0, hy, M, 2.0 * (double)(hx > hy ? hx : hy), colp, rowp, geo);
         const int32_t ranges[2][4] = {{colp.x, colp.y, colp.z, colp.w}, {rowp.x, rowp.y, rowp.z, rowp.w}};
         int ja, jb;
         unpack_range(geo.x, ja, jb);
