@@ -358,12 +358,23 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     uint32_t* counter = err + 1;
 
     mark(0);
-    launch_zero_u32(err, 2, s);
-    launch_zero_u32(reinterpret_cast<uint32_t*>(keys), (size_t)plan.nres * 2, s);
-    launch_zero_u32(reinterpret_cast<uint32_t*>(stt), (size_t)plan.nres * sizeof(PeakState) / 4, s);
-    launch_zero_u32(reinterpret_cast<uint32_t*>(res), (size_t)plan.nres * sizeof(aoresp_result) / 4, s);
+    // every accumulator and flag of the plan starts at zero: one launch
+    ZeroList zl{};
+    auto zero = [&zl](void* p, size_t words) {
+        zl.ptr[zl.count] = static_cast<uint32_t*>(p);
+        zl.words[zl.count] = words;
+        ++zl.count;
+    };
+    zero(err, 2);
+    zero(keys, (size_t)plan.nres * 2);
+    zero(stt, (size_t)plan.nres * sizeof(PeakState) / 4);
+    zero(res, (size_t)plan.nres * sizeof(aoresp_result) / 4);
+    zero(w.grid.ptr, plan.grid_cells);
+    zero(w.fine.ptr, plan.maxM > 0 ? plan.fine_cells : 0);
+    zero(w.hist.ptr, plan.hist_cells);
+    zero(w.icount.ptr, (size_t)plan.nres * kCountSlots);
+    launch_zero_list(zl, s);
     launch_arc_setup(P, Q, N, insts, ninst, R, s);
-    launch_zero_u32(w.grid.as<uint32_t>(), plan.grid_cells, s);
     mark(1);
     launch_vote(R, insts, vote_items, (int)plan.vote_items.size(), counter, w.grid.as<uint32_t>(), err,
                 ctx->cu_count, s);
@@ -373,7 +384,6 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
         launch_peak_finish(insts, ninst, keys, stt, t, s);
     }
     mark(3);
-    if (plan.maxM > 0) launch_zero_u32(w.fine.as<uint32_t>(), plan.fine_cells, s);
     for (int t = 0; t < plan.max_npk; ++t) {
         if (plan.maxM > 0) {
             launch_fine_vote(R, insts, list_items, (int)plan.list_items.size(), stt, t, w.fine.as<uint32_t>(), err,
@@ -382,7 +392,6 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
         launch_fine_peak(w.fine.as<uint32_t>(), insts, ninst, stt, t, s);
     }
     mark(4);
-    launch_zero_u32(w.hist.as<uint32_t>(), plan.hist_cells, s);
     launch_angle_hist(P, Q, N, insts, corr_items, (int)plan.corr_items.size(), stt, w.hist.as<uint32_t>(),
                       plan.hist_lds, s);
     for (int t = 0; t < plan.max_npk; ++t) launch_angle_peak(w.hist.as<uint32_t>(), insts, ninst, stt, t, res, s);

@@ -91,6 +91,14 @@ size_t coarse_lds_bytes();
 void init_kernel_attributes();   // once per device, before the first launch
 
 void launch_zero_u32(uint32_t* p, size_t count, hipStream_t s);
+// Up to kZeroSpans buffers of u32 words zeroed by one launch.
+constexpr int kZeroSpans = 8;
+struct ZeroList {
+    uint32_t* ptr[kZeroSpans];
+    size_t words[kZeroSpans];
+    int count;
+};
+void launch_zero_list(const ZeroList& zl, hipStream_t s);
 void launch_arc_setup(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, ArcRecs recs,
                       hipStream_t s);
 // items: int4 (inst, mode | band << 1, i0, i1), processed by `blocks`
@@ -114,6 +122,7 @@ void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* in
                        const PeakState* st, uint32_t* hist_arena, size_t lds_bytes, hipStream_t s);
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                        aoresp_result* res, hipStream_t s);
+// partial: nres * kCountSlots counters, zero on entry.
 void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, const PeakState* st,
                     aoresp_result* res, int nres, uint8_t* masks, uint32_t* partial, hipStream_t s);
 

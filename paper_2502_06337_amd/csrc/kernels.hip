@@ -1023,6 +1023,17 @@ __global__ void k_zero_u32(uint32_t* p, size_t count) {
         p[i] = 0u;
 }
 
+// Every span of the list zeroed by one grid-stride pass.
+__global__ void k_zero_list(ZeroList zl) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    const size_t t0 = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int k = 0; k < zl.count; ++k) {
+        uint32_t* p = zl.ptr[k];
+        const size_t n = zl.words[k];
+        for (size_t i = t0; i < n; i += stride) p[i] = 0u;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Launchers
 // --------------------------------------------------------------------------
@@ -1044,6 +1055,15 @@ void init_kernel_attributes() {
     set_lds_limit((const void*)k_vote);
     set_lds_limit((const void*)k_fine_vote);
     set_lds_limit((const void*)k_angle_hist);
+}
+
+void launch_zero_list(const ZeroList& zl, hipStream_t s) {
+    size_t most = 0;
+    for (int k = 0; k < zl.count; ++k) most = zl.words[k] > most ? zl.words[k] : most;
+    if (!most) return;
+    size_t blocks = (most + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_list, dim3((unsigned)blocks), dim3(256), 0, s, zl);
 }
 
 void launch_zero_u32(uint32_t* p, size_t count, hipStream_t s) {
@@ -1107,7 +1127,6 @@ void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst,
 void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, const PeakState* st,
                     aoresp_result* res, int nres, uint8_t* masks, uint32_t* partial, hipStream_t s) {
     if (N <= 0) return;
-    launch_zero_u32(partial, (size_t)nres * kCountSlots, s);
     const int64_t per_block = 256 * kInlierSub;
     hipLaunchKernelGGL(k_inliers, dim3((unsigned)((N + per_block - 1) / per_block)), dim3(256), 0, s, P, Q, N, insts,
                        ninst, st, res, masks, partial);
