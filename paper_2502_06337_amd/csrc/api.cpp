@@ -317,12 +317,10 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.hist.ensure(plan.hist_cells * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
-    if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
-    if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
-    if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
+    const OutLayout ol(plan.nres);
+    if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
     if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
-    if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
-    if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
+    if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
     const size_t o_vote = (b_inst + 255) / 256 * 256;
@@ -351,10 +349,11 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     const int4* list_items = reinterpret_cast<const int4*>(db + o_list);
 
     ArcRecs R{w.abc.as<float4>(), w.colp.as<int4>(), w.rowp.as<int4>(), w.geo.as<int4>()};
-    PeakState* stt = w.st.as<PeakState>();
-    aoresp_result* res = w.res.as<aoresp_result>();
+    char* ob = w.out.as<char>();
+    PeakState* stt = reinterpret_cast<PeakState*>(ob + ol.o_st);
+    aoresp_result* res = reinterpret_cast<aoresp_result*>(ob + ol.o_res);
     unsigned long long* keys = w.keys.as<unsigned long long>();
-    uint32_t* err = w.err.as<uint32_t>();
+    uint32_t* err = reinterpret_cast<uint32_t*>(ob + ol.o_err);
     uint32_t* counter = err + 1;
 
     mark(0);
@@ -365,10 +364,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
         zl.words[zl.count] = words;
         ++zl.count;
     };
-    zero(err, 2);
+    zero(w.out.ptr, ol.bytes / 4);
     zero(keys, (size_t)plan.nres * 2);
-    zero(stt, (size_t)plan.nres * sizeof(PeakState) / 4);
-    zero(res, (size_t)plan.nres * sizeof(aoresp_result) / 4);
     zero(w.grid.ptr, plan.grid_cells);
     zero(w.fine.ptr, plan.maxM > 0 ? plan.fine_cells : 0);
     zero(w.hist.ptr, plan.hist_cells);
@@ -411,24 +408,24 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
 }
 
 aoresp_status fetch_plan(Workspace& w, const Plan& plan, hipStream_t s) {
+    const OutLayout ol(plan.nres);
     aoresp_status st;
-    if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
-    if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
-    AOR_HIP(hipMemcpyAsync(w.h_res.ptr, w.res.ptr, sizeof(aoresp_result) * plan.nres, hipMemcpyDeviceToHost, s));
-    AOR_HIP(hipMemcpyAsync(w.h_st.ptr, w.st.ptr, sizeof(PeakState) * plan.nres, hipMemcpyDeviceToHost, s));
-    uint32_t* herr = reinterpret_cast<uint32_t*>(w.h_st.as<char>() + sizeof(PeakState) * plan.nres);
-    AOR_HIP(hipMemcpyAsync(herr, w.err.ptr, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
+    // results, peak states and the flag in one copy
+    AOR_HIP(hipMemcpyAsync(w.h_out.ptr, w.out.ptr, ol.o_err + sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     return AORESP_OK;
 }
 
 aoresp_status collect_plan(Workspace& w, const Plan& plan, aoresp_result* out, std::vector<int>& valid) {
-    const uint32_t* herr = reinterpret_cast<const uint32_t*>(w.h_st.as<char>() + sizeof(PeakState) * plan.nres);
+    const OutLayout ol(plan.nres);
+    const char* hb = w.h_out.as<char>();
+    const uint32_t* herr = reinterpret_cast<const uint32_t*>(hb + ol.o_err);
     if (*herr) {
         if (debug_on()) fprintf(stderr, "aoresp: internal check flag 0x%x\n", *herr);
         return AORESP_EDEVICE;
     }
-    const aoresp_result* hr = w.h_res.as<aoresp_result>();
-    const PeakState* hs = w.h_st.as<PeakState>();
+    const aoresp_result* hr = reinterpret_cast<const aoresp_result*>(hb + ol.o_res);
+    const PeakState* hs = reinterpret_cast<const PeakState*>(hb + ol.o_st);
     valid.assign(plan.nres, 0);
     for (int t = 0; t < plan.nres; ++t) {
         out[t] = hr[t];
@@ -501,12 +498,10 @@ aoresp_status reserve_plan(Workspace& w, const Plan& plan) {
     if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.hist.ensure(plan.hist_cells * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
-    if ((st = w.st.ensure((size_t)plan.nres * sizeof(PeakState))) != AORESP_OK) return st;
-    if ((st = w.res.ensure((size_t)plan.nres * sizeof(aoresp_result))) != AORESP_OK) return st;
-    if ((st = w.err.ensure(2 * sizeof(uint32_t))) != AORESP_OK) return st;
+    const OutLayout ol(plan.nres);
+    if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
     if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
-    if ((st = w.h_res.ensure((size_t)plan.nres * sizeof(aoresp_result) + 16)) != AORESP_OK) return st;
-    if ((st = w.h_st.ensure((size_t)plan.nres * sizeof(PeakState) + 16)) != AORESP_OK) return st;
+    if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
     const size_t total = plan_blob_bytes(plan);
     if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
     if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
@@ -518,10 +513,10 @@ void release_workspace(Workspace& w) {
     w.gexec = nullptr;
     if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
     w.cap_stream = nullptr;
-    DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.st,
-                      &w.res, &w.err, &w.icount, &w.plan, &w.P, &w.Q, &w.masks};
+    DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.out,
+                      &w.icount, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
-    HostBuf* hb[] = {&w.h_plan, &w.h_res, &w.h_st};
+    HostBuf* hb[] = {&w.h_plan, &w.h_out};
     for (HostBuf* b : hb) {
         if (b->ptr) (void)hipHostFree(b->ptr);
         b->ptr = nullptr;

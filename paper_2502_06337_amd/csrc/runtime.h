@@ -47,15 +47,30 @@ struct HostBuf {
     T* as() const { return static_cast<T*>(ptr); }
 };
 
+// A plan's outputs in one device buffer (and its pinned mirror), so that one
+// copy brings them back: results, peak states, then the internal-check flag
+// and the coarse vote's work counter.
+struct OutLayout {
+    size_t o_res, o_st, o_err, bytes;
+    explicit OutLayout(int nres) {
+        auto up = [](size_t b) { return (b + 15) / 16 * 16; };
+        o_res = 0;
+        o_st = up((size_t)nres * sizeof(aoresp_result));
+        o_err = o_st + up((size_t)nres * sizeof(PeakState));
+        bytes = o_err + 16;
+    }
+};
+
 // Everything a batch enqueues into.
 struct Workspace {
     DevBuf abc, colp, rowp, geo;    // per global column
     DevBuf grid, fine, hist;        // arenas
-    DevBuf keys, st, res, err;      // per result slot (+ err flag, vote counter)
+    DevBuf keys;                    // per result slot: peak search keys
+    DevBuf out;                     // results, peak states, flag and counter (OutLayout)
     DevBuf icount;                  // partial inlier counters (kCountSlots per result slot)
     DevBuf plan;                    // instance table + work items
     DevBuf P, Q, masks;             // staging for host-pointer entry points
-    HostBuf h_plan, h_res, h_st;    // pinned mirrors
+    HostBuf h_plan, h_out;          // pinned mirrors
     hipStream_t stream = nullptr;   // internal stream for host-pointer calls
     hipStream_t cap_stream = nullptr;   // stream that batched plans are captured on
     hipGraphExec_t gexec = nullptr;     // last captured plan, updated in place when the topology repeats
