@@ -316,6 +316,20 @@ AOR_HD __forceinline__ void walk_start(float sb, float sc, float aL, float bL, f
     find_transition(sb, sc, xx, ax, y0, hy, g, lo, hi, flo, fhi, bad);
 }
 
+// Seed for a certified part.  Where the octant's slope is at most 1 the
+// crossing is well conditioned (|c y + b| >= |d| / sqrt(2) there), so the
+// binary32 root of the scaled equation lies within a small fraction of a row
+// of the exact one; the exact search from the seed fixes the transition.
+AOR_HD __forceinline__ void walk_start_cert(float sb, float sc, float aL, float bL, float c, int sel, float x0,
+                                            float hx, float y0, float hy, int cs, float xx, float ax, int& lo, int& hi,
+                                            float& flo, float& fhi, uint32_t& bad) {
+    const float inv = 1.0f / ((fabsf(aL) + fabsf(bL)) + c);
+    const float yr = cross_root_f(aL * inv, bL * inv, c * inv, x0 + (float)cs * hx, sel);
+    const float gt = floorf((yr - y0) / hy);
+    const int g = !(gt > -16.0f) ? -16 : (gt > 16384.0f ? 16384 : (int)gt);
+    find_transition(sb, sc, xx, ax, y0, hy, g, lo, hi, flo, fhi, bad);
+}
+
 // General walk: an exact search on every line.  Used on the few lines where an
 // octant is not known to be monotone with |slope| <= 1 (the line through its
 // extreme point, the three lines past a 45-degree point).
@@ -381,7 +395,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
     float xx = x * x, ax = sa * x;
     int lo, hi;
     float flo, fhi;
-    walk_start(sb, sc, aL, bL, c, sel, x0, hx, y0, hy, cs, xx, ax, lo, hi, flo, fhi, bad);
+    walk_start_cert(sb, sc, aL, bL, c, sel, x0, hx, y0, hy, cs, xx, ax, lo, hi, flo, fhi, bad);
     // certificates of the bracketing vertices after the search
     bool cb = (hi == lo - 1) ? (fhi > T) : true;
     bool ca = (hi == lo - 1) ? (flo < -T) : true;
