@@ -74,6 +74,11 @@ __global__ __launch_bounds__(256) void k_arc_setup(const float* __restrict__ P, 
 // Coarse accumulator: banded LDS tiles, persistent work-groups
 // --------------------------------------------------------------------------
 
+// Set bits of a wave mask in the lanes below this one.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Cells of a band tile: 16-bit counters, the cells (j, k) and (j + 1, k) of
 // an even/odd line pair in the low and high half of one word, word rows of
 // Sw = G + 1 words per line pair (pair m, cross k at m * Sw + k).  The lanes
@@ -146,7 +151,6 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
     uint32_t* rline = rbody + kRingBody;
     uint32_t* sinkrow = smem + kTileWords + kWaves * (kRingBody + kRingLine);   // 64 words, never read
     int16_t* dlim = reinterpret_cast<int16_t*>(sinkrow + 64);
-    const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t bad = 0;
 
     for (;;) {
@@ -187,7 +191,8 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         int step = 4;
         bool draining = false;
         int64_t li = 0;
-        int4 pc = make_int4(0, 0, 0, 0), geo = pc;
+        int4 pc = make_int4(0, 0, 0, 0);
+        int slo_e = 0, shi_e = 0, slo_o = 0, shi_o = 0;   // body lines of the even / odd octants
         int4 pc_next = pc;
         if (g0 + lane < nli) pc_next = prange[base + g0 + lane];
         for (;;) {
@@ -287,7 +292,13 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                         any |= max(s, band0) < min(e, band0 + bwb);
                     }
                 }
-                if (any) geo = R.geo[base + li];
+                if (any) {
+                    // the body range depends on the octant only through its parity
+                    const int4 geo = R.geo[base + li];
+                    int d;
+                    octant_walk_info(mode, 0, geo, d, slo_e, shi_e);
+                    octant_walk_info(mode, 1, geo, d, slo_o, shi_o);
+                }
                 step = __ballot(any) ? 0 : 4;
                 if (!any) li = nli;   // nothing of this one in the band
                 continue;
@@ -302,8 +313,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     unpack_range(pr, s, e);
                     const int cs = max(s, band0), ce = min(e, band0 + bwb);
                     if (cs < ce) {
-                        int dir, slo, shi;
-                        octant_walk_info(mode, p, geo, dir, slo, shi);
+                        const int slo = (p & 1) ? slo_o : slo_e, shi = (p & 1) ? shi_o : shi_e;
                         int2 parts[3];
                         split_piece(cs, ce, slo, shi, parts);
                         hb = parts[1].x < parts[1].y;
@@ -313,10 +323,10 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                 }
                 const uint32_t key = ((uint32_t)li << 4) | ((uint32_t)p << 2);
                 const unsigned long long mb = __ballot(hb), m0 = __ballot(h0), m2 = __ballot(h2);
-                if (hb) rbody[(bh + bn + __popcll(mb & below)) & (kRingBody - 1)] = key | 1u;
+                if (hb) rbody[(bh + bn + lanes_below(mb)) & (kRingBody - 1)] = key | 1u;
                 const int n0 = __popcll(m0);
-                if (h0) rline[(lh + ln + __popcll(m0 & below)) & (kRingLine - 1)] = key | 0u;
-                if (h2) rline[(lh + ln + n0 + __popcll(m2 & below)) & (kRingLine - 1)] = key | 2u;
+                if (h0) rline[(lh + ln + lanes_below(m0)) & (kRingLine - 1)] = key | 0u;
+                if (h2) rline[(lh + ln + n0 + lanes_below(m2)) & (kRingLine - 1)] = key | 2u;
                 bn += __popcll(mb);
                 ln += n0 + __popcll(m2);
                 ++step;
