@@ -75,18 +75,36 @@ AOR_HD __forceinline__ double cross_root(double a, double b, double c, double x,
     return K / qq;
 }
 
+// Reciprocal and square root to about one ulp (the hardware instructions on
+// the GPU), for values that only seed an exact search.
+AOR_HD __forceinline__ float seed_rcp(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#else
+    return 1.0f / x;
+#endif
+}
+AOR_HD __forceinline__ float seed_sqrt(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#else
+    return sqrtf(x);
+#endif
+}
+
 // The same root in binary32, for a, b, c scaled to |a| + |b| + |c| = 1 (the
-// roots do not depend on the scale).  Used only to seed an exact search.
+// roots do not depend on the scale), to about an ulp.  Used only to seed an
+// exact search.
 AOR_HD __forceinline__ float cross_root_f(float a, float b, float c, float x, int sel) {
     const float K = c * (x * x - 1.0f) + 2.0f * a * x;
-    if (c == 0.0f) return -K / (2.0f * b);
+    if (c == 0.0f) return -K * seed_rcp(2.0f * b);
     const float t = c * x + a;
     float disc = (a * a + b * b + c * c) - t * t;
     if (disc < 0.0f) disc = 0.0f;
-    const float qq = -(b + copysignf(sqrtf(disc), b));
+    const float qq = -(b + copysignf(seed_sqrt(disc), b));
     const bool r1_wanted = (sel == 0) != (bool)signbit(b);
-    if (r1_wanted || qq == 0.0f) return qq / c;
-    return K / qq;
+    if (r1_wanted || qq == 0.0f) return qq * seed_rcp(c);
+    return K * seed_rcp(qq);
 }
 
 AOR_HD __forceinline__ int32_t pack_range(int s, int e) {

@@ -323,9 +323,9 @@ AOR_HD __forceinline__ void walk_start(float sb, float sc, float aL, float bL, f
 AOR_HD __forceinline__ void walk_start_cert(float sb, float sc, float aL, float bL, float c, int sel, float x0,
                                             float hx, float y0, float hy, int cs, float xx, float ax, int& lo, int& hi,
                                             float& flo, float& fhi, uint32_t& bad) {
-    const float inv = 1.0f / ((fabsf(aL) + fabsf(bL)) + c);
+    const float inv = seed_rcp((fabsf(aL) + fabsf(bL)) + c);
     const float yr = cross_root_f(aL * inv, bL * inv, c * inv, x0 + (float)cs * hx, sel);
-    const float gt = floorf((yr - y0) / hy);
+    const float gt = floorf((yr - y0) * seed_rcp(hy));
     const int g = !(gt > -16.0f) ? -16 : (gt > 16384.0f ? 16384 : (int)gt);
     find_transition(sb, sc, xx, ax, y0, hy, g, lo, hi, flo, fhi, bad);
 }
