@@ -62,13 +62,16 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
     return 0u;
 }
 
-// Certification threshold of the coarse walk, T = 2e-6 (|a| + |b| + |c|); a
+// Certification threshold of the coarse walk, T = 1.2e-6 (|a| + |b| + |c|); a
 // refinement grid uses 1.5 T.  Evaluated vertices have |u| <= 1 and |v| <=
-// 1 + 4h <= 1.125 (the crossing stays within the frame plus the clip margin).
-// Let E bound the binary32 error of F at a vertex with sigma*F > T.  On the
-// coarse lattice W is exact, and the three products, the inner sum and the
-// outer sum give E <= 2^-24 (1.27 |c| + 4.5 (|a| + |b|)) <= 2^-21 (|a| + |b| +
-// |c|); a refinement grid rounds W as well, adding 2^-22 |c|.
+// 1 + 4h <= 1.125 (the crossing stays within the frame plus the clip margin),
+// so |W| <= 1.27.  Let E bound the binary32 error of F at a vertex with
+// sigma*F > T.  On the coarse lattice W is exact; the products c*W, a*u, b*v,
+// the inner sum and the outer sum each round once (relative 2^-24), and the
+// doubling is exact, so |F~ - F| <= 2^-24 (1.27 |c| + 4.5 (|a| + |b|)) +
+// 2^-24 |F~|, and near the threshold E <= 4.5 * 2^-24 (|a| + |b| + |c|).  A
+// refinement grid rounds W as well (at most 2^-22, times |c|), so there
+// E <= 5.3 * 2^-24 (|a| + |b| + |c|).
 // (i) sigma*F > T gives an exact F > T - E; along a vertex line |dF/dy| =
 // 2 |c y + b| <= L = 2 (1.125 |c| + |b|) <= 3.01 |d|, so the vertex lies
 // beyond the curve by a cross gap g >= (T - E) / L.  (ii) The gap carries over
@@ -78,11 +81,10 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
 // R = |d| / c >= 1) |F| = c |rho - R| (rho + R) >= 2 |d| delta (1 - delta / 2R),
 // and |F| = 2 |d| delta for a line, so binary32 gets the sign of every vertex
 // farther than E / (1.99 |d|).  T must therefore exceed
-// E (1 + sqrt(2) L / (1.99 |d|)) <= 3.14 E: 1.5e-6 (|a| + |b| + |c|) on the
-// coarse lattice and 2.25e-6 on a refinement grid, a margin of 1.33x for both
-// thresholds (2.4x on the coarse lattice's own 4.5 term).
+// E (1 + sqrt(2) L / (1.99 |d|)) <= 3.14 E: 8.4e-7 (|a| + |b| + |c|) on the
+// coarse lattice and 9.9e-7 on a refinement grid, margins of 1.42x and 1.8x.
 AOR_HD __forceinline__ float cert_threshold(float a, float b, float c) {
-    return 2.0e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
+    return 1.2e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
 }
 constexpr float kFineCertScale = 1.5f;   // refinement grids certify with 1.5 T
 
