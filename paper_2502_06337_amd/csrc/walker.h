@@ -410,6 +410,10 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
     }
     const int off = dir < 0 ? 1 : 0;
     bool clean = cb && ca && hi == lo - 1;
+    // the certificates live as bits of an integer between lines (bit 0: cb,
+    // bit 1: ca), so the clean path, which never changes them, needs no
+    // execution-mask bookkeeping for them
+    int cert = (cb ? 1 : 0) | (ca ? 2 : 0);
     int r = lo - off;   // the row evaluated next while clean
     float yr = y0 + (float)r * hy;
     float dy_up = (float)(1 - off) * hy, dy_dn = -(float)off * hy;   // exact: off is 0 or 1
@@ -446,6 +450,8 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             lastf = f;
             continue;
         }
+        cb = (cert & 1) != 0;
+        ca = (cert & 2) != 0;
         if (lastf != 0.0f) {
             // the evaluated vertex of the previous line was not certified
             lo = r + off;
@@ -474,9 +480,8 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
                 emit(j, (lo < lo1 ? lo : lo1) - 1, (lo > lo1 ? lo : lo1) - 1);
                 lo = lo1;
                 hi = lo1 - 1;
-                cb = cb1;
-                ca = ca1;
-                clean = cb && ca;
+                cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
+                clean = cb1 && ca1;
                 r = lo - off;
                 if (kLattice) yr = y0 + (float)r * hy;
                 continue;
@@ -521,9 +526,8 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         emit(j, (lo < lo1 ? lo : lo1) - 1, hi > hi1 ? hi : hi1);
         lo = lo1;
         hi = hi1;
-        cb = cb1;
-        ca = ca1;
-        clean = cb && ca && hi == lo - 1;
+        cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
+        clean = cb1 && ca1 && hi == lo - 1;
         r = lo - off;
         if (kLattice) yr = y0 + (float)r * hy;
     }
