@@ -409,7 +409,8 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         ca = vertex_F(sb, sc, xx, ax, ya) < -T;
     }
     const int off = dir < 0 ? 1 : 0;
-    bool clean = cb && ca && hi == lo - 1;
+    // clean is kept as an integer too, for the same reason as cert below
+    int clean = (cb && ca && hi == lo - 1) ? 1 : 0;
     // the certificates live as bits of an integer between lines (bit 0: cb,
     // bit 1: ca), so the clean path, which never changes them, needs no
     // execution-mask bookkeeping for them
@@ -435,7 +436,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         ax = sa * x;
         // evaluated on every lane; only clean lanes use it
         const float f = vertex_F(sb, sc, xx, ax, kLattice ? yr : y0 + (float)r * hy);
-        if (clean && f != 0.0f) {
+        if (clean != 0 && f != 0.0f) {
             if constexpr (Emit::kAudit) {
                 // test builds only: the certificates vouch for sigma*F > 0 at
                 // row r - 1 and sigma*F < 0 at row r + 1 of this line
@@ -446,7 +447,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             emit.pair(cur, r, up != (off != 0));
             r += (up ? 1 : 0) - off;
             if (kLattice) yr += up ? dy_up : dy_dn;
-            clean = fabsf(f) > T;
+            clean = fabsf(f) > T ? 1 : 0;
             lastf = f;
             continue;
         }
@@ -460,7 +461,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             ca = !(lastf < 0.0f);
             lastf = 0.0f;
         }
-        if (clean) {
+        if (clean != 0) {
             // zero vertex on the evaluated row: rebuild the full state
             lo = r + off;
             hi = lo - 1;
@@ -481,7 +482,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
                 lo = lo1;
                 hi = lo1 - 1;
                 cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
-                clean = cb1 && ca1;
+                clean = (cb1 && ca1) ? 1 : 0;
                 r = lo - off;
                 if (kLattice) yr = y0 + (float)r * hy;
                 continue;
@@ -527,7 +528,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         lo = lo1;
         hi = hi1;
         cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
-        clean = cb1 && ca1 && hi == lo - 1;
+        clean = (cb1 && ca1 && hi == lo - 1) ? 1 : 0;
         r = lo - off;
         if (kLattice) yr = y0 + (float)r * hy;
     }
