@@ -409,12 +409,18 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         ca = vertex_F(sb, sc, xx, ax, ya) < -T;
     }
     const int off = dir < 0 ? 1 : 0;
-    // clean is kept as an integer too, for the same reason as cert below
-    int clean = (cb && ca && hi == lo - 1) ? 1 : 0;
-    // the certificates live as bits of an integer between lines (bit 0: cb,
-    // bit 1: ca), so the clean path, which never changes them, needs no
-    // execution-mask bookkeeping for them
+    // The state between lines lives in registers that the clean path either
+    // leaves alone or overwrites, never in execution masks (whose merging at
+    // every join would cost scalar instructions on each line).  cert holds the
+    // certificates (bit 0: cb, bit 1: ca).  lastf holds the state class:
+    //   |lastf| > T      clean (the value evaluated on the previous line, or
+    //                    +inf after a general step that ended clean);
+    //   0 < |lastf| <= T the previous line left the clean state there: lo,
+    //                    hi, cb and ca are rebuilt from r and lastf's sign;
+    //   lastf == 0       not clean, lo, hi and cert hold the state.
+    const bool clean0 = cb && ca && hi == lo - 1;
     int cert = (cb ? 1 : 0) | (ca ? 2 : 0);
+    const float kCleanMark = __builtin_huge_valf();
     int r = lo - off;   // the row evaluated next while clean
     float yr = y0 + (float)r * hy;
     float dy_up = (float)(1 - off) * hy, dy_dn = -(float)off * hy;   // exact: off is 0 or 1
@@ -424,19 +430,14 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
     __asm__("" : "+v"(dy_up), "+v"(dy_dn));
 #endif
     auto cur = emit.start(cs, off);
-    // lastf: the value evaluated on the previous line if that line took the
-    // clean step, else 0.  A lane that is no longer clean and has lastf != 0
-    // left the clean state there (|F| <= T): lo, hi, cb and ca are rebuilt
-    // from r and lastf.  (A lane still clean that meets a zero vertex rebuilds
-    // its state from r alone, overriding that.)
-    float lastf = 0.0f;
+    float lastf = clean0 ? kCleanMark : 0.0f;
     for (int j = cs; j < ce; ++j, cur = emit.next(cur)) {
         x += hx;
         xx = x * x;
         ax = sa * x;
         // evaluated on every lane; only clean lanes use it
         const float f = vertex_F(sb, sc, xx, ax, kLattice ? yr : y0 + (float)r * hy);
-        if (clean != 0 && f != 0.0f) {
+        if (fabsf(lastf) > T && f != 0.0f) {
             if constexpr (Emit::kAudit) {
                 // test builds only: the certificates vouch for sigma*F > 0 at
                 // row r - 1 and sigma*F < 0 at row r + 1 of this line
@@ -447,21 +448,21 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             emit.pair(cur, r, up != (off != 0));
             r += (up ? 1 : 0) - off;
             if (kLattice) yr += up ? dy_up : dy_dn;
-            clean = fabsf(f) > T ? 1 : 0;
             lastf = f;
             continue;
         }
+        const bool clean = fabsf(lastf) > T;
         cb = (cert & 1) != 0;
         ca = (cert & 2) != 0;
-        if (lastf != 0.0f) {
+        if (!clean && lastf != 0.0f) {
             // the evaluated vertex of the previous line was not certified
             lo = r + off;
             hi = lo - 1;
             cb = !(lastf > 0.0f);
             ca = !(lastf < 0.0f);
-            lastf = 0.0f;
         }
-        if (clean != 0) {
+        lastf = 0.0f;
+        if (clean) {
             // zero vertex on the evaluated row: rebuild the full state
             lo = r + off;
             hi = lo - 1;
@@ -482,7 +483,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
                 lo = lo1;
                 hi = lo1 - 1;
                 cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
-                clean = (cb1 && ca1) ? 1 : 0;
+                lastf = (cb1 && ca1) ? kCleanMark : 0.0f;
                 r = lo - off;
                 if (kLattice) yr = y0 + (float)r * hy;
                 continue;
@@ -528,7 +529,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         lo = lo1;
         hi = hi1;
         cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
-        clean = (cb1 && ca1 && hi == lo - 1) ? 1 : 0;
+        lastf = (cb1 && ca1 && hi == lo - 1) ? kCleanMark : 0.0f;
         r = lo - off;
         if (kLattice) yr = y0 + (float)r * hy;
     }
