@@ -60,6 +60,30 @@ def test_coarse_grid_bit_exact(aor, orc, G, seed):
     assert diff.size == 0, (len(diff), diff[:10], g_gpu[tuple(diff[0])], g_or[tuple(diff[0])])
 
 
+@pytest.mark.parametrize("G", [512, 2048, 4096])
+def test_coarse_grid_bit_exact_large_grids(aor, orc, G):
+    """Band widths of 128, 32 and 16 lines (16-bit tiles of 65536 cells)."""
+    inst = synth.make_instance(1500, 3100 + G)
+    g_gpu = gpu_grid(aor, inst.P, inst.Q, G)
+    g_or = orc.coarse_grid(inst.P, inst.Q, G)
+    diff = np.argwhere(g_gpu != g_or)
+    assert diff.size == 0, (len(diff), diff[:10])
+
+
+def test_coarse_grid_counts_beyond_16_bits(aor, orc):
+    """70000 copies of one correspondence at G = 1024: every cell on its curve
+    collects 70000 votes, 64512 of them from one work item; the 16-bit band
+    counters must neither overflow nor carry into the neighbouring line."""
+    G, n = 1024, 70000
+    one = synth.make_instance(1, 77)
+    P = np.repeat(one.P, n, axis=1)
+    Q = np.repeat(one.Q, n, axis=1)
+    g_gpu = gpu_grid(aor, P, Q, G)
+    g_one = orc.coarse_grid(one.P, one.Q, G).astype(np.uint64)
+    assert g_one.sum() > 0
+    assert np.array_equal(g_gpu.astype(np.uint64), g_one * n)
+
+
 def special_cases():
     """Lines, the unit circle, axis-aligned and near-degenerate displacements."""
     rows = []
