@@ -9,9 +9,10 @@ few pure-numpy helpers used by the pins.
 Parity status per function (see the module docstring of each test file for
 the pins):
   coarse vote, fine vote, peak, top-k, axis, angle bin/histogram, rotation,
-  inliers -- pinned (closed forms, brute force, invariants, noise-free
-  recovery); end-to-end accuracy against the paper's reported error -- parity
-  unpinned (the paper's figures are not recoverable).
+  inliers, least-squares rotation on the inlier set -- pinned (closed forms,
+  brute force, invariants, noise-free recovery); end-to-end accuracy against
+  the paper's reported error -- parity unpinned (the paper's figures are not
+  recoverable).
 """
 from __future__ import annotations
 
@@ -259,6 +260,24 @@ def rotation_error_deg(Rgt, R) -> float:
     Rgt = np.ascontiguousarray(Rgt, dtype=np.float64).ravel()
     R = _f32(R).ravel()
     return float(lib().or_rotation_error_deg(Rgt.ctypes.data_as(C.POINTER(C.c_double)), _ptr(R, _fp)))
+
+
+def ls_rotation(P, Q, mask) -> np.ndarray:
+    """Least-squares rotation on an inlier set (a refinement step after the
+    inlier test of Eq. (1); not part of the paper's Algorithm 1): the proper
+    rotation R minimising sum over the set of ||R p_i - q_i||^2, in float64, by
+    the SVD of H = sum p_i q_i^T (Kabsch): with H = U S V^T, R = V D U^T where
+    D = diag(1, 1, sign det(V U^T)).  Fewer than three members: None."""
+    P = np.asarray(P, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    m = np.asarray(mask).astype(bool)
+    if int(m.sum()) < 3:
+        return None
+    H = P[:, m] @ Q[:, m].T
+    U, _, Vt = np.linalg.svd(H)
+    V = Vt.T
+    d = 1.0 if np.linalg.det(V @ U.T) > 0 else -1.0
+    return V @ np.diag([1.0, 1.0, d]) @ U.T
 
 
 def suppressed(G: int, rad: int, px: int, py: int, ix: int, iy: int) -> bool:

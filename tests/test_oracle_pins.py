@@ -434,3 +434,86 @@ def test_enodata(orc):
     P = np.ones((3, 5), dtype=np.float32)
     res = orc.solve(P, P, G=64, B=36)
     assert res["status"] == -4
+
+
+# ------------------------------------------- least-squares rotation (inliers)
+def _random_rotation(rng):
+    q = rng.normal(size=4)
+    q /= np.linalg.norm(q)
+    w, x, y, z = q
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def _objective(R, P, Q):
+    return float(np.sum((R @ P - Q) ** 2))
+
+
+def test_ls_rotation_noise_free_recovery_and_equivariance(orc):
+    rng = np.random.default_rng(5)
+    for _ in range(10):
+        R = _random_rotation(rng)
+        P = rng.uniform(-1, 1, (3, 50))
+        m = np.ones(50, bool)
+        assert np.allclose(orc.ls_rotation(P, R @ P, m), R, atol=1e-12)
+        Q = R @ P + 0.01 * rng.normal(size=(3, 50))
+        R0 = orc.ls_rotation(P, Q, m)
+        S, Tm = _random_rotation(rng), _random_rotation(rng)
+        assert np.allclose(orc.ls_rotation(P, S @ Q, m), S @ R0, atol=1e-12)
+        assert np.allclose(orc.ls_rotation(Tm @ P, Q, m), R0 @ Tm.T, atol=1e-12)
+
+
+def test_ls_rotation_is_the_minimiser(orc):
+    """Brute force: no sampled or nearby rotation does better, and the result
+    is a proper rotation even where the best orthogonal map is a reflection."""
+    rng = np.random.default_rng(6)
+    cases = []
+    R = _random_rotation(rng)
+    P = rng.uniform(-1, 1, (3, 30))
+    cases.append((P, R @ P + 0.05 * rng.normal(size=(3, 30))))
+    P2 = rng.uniform(-1, 1, (3, 12))
+    cases.append((P2, -P2))                      # point reflection: det(V U^T) = -1
+    for P, Q in cases:
+        Rl = orc.ls_rotation(P, Q, np.ones(P.shape[1], bool))
+        assert abs(np.linalg.det(Rl) - 1.0) < 1e-12 and np.allclose(Rl @ Rl.T, np.eye(3), atol=1e-12)
+        best = _objective(Rl, P, Q)
+        for _ in range(3000):
+            assert best <= _objective(_random_rotation(rng), P, Q) + 1e-12
+        for _ in range(300):
+            w = rng.normal(size=3) * 1e-3
+            K = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+            assert best <= _objective(Rl @ (np.eye(3) + K + K @ K / 2), P, Q) + 1e-12
+
+
+def test_ls_rotation_matches_quaternion_method(orc):
+    """Horn's quaternion solution (largest eigenvector of the 4x4 matrix built
+    from H) gives the same rotation."""
+    rng = np.random.default_rng(7)
+    for _ in range(10):
+        R = _random_rotation(rng)
+        P = rng.uniform(-1, 1, (3, 40))
+        Q = R @ P + 0.02 * rng.normal(size=(3, 40))
+        S = P @ Q.T
+        N = np.array([[S[0, 0] + S[1, 1] + S[2, 2], S[1, 2] - S[2, 1], S[2, 0] - S[0, 2], S[0, 1] - S[1, 0]],
+                      [S[1, 2] - S[2, 1], S[0, 0] - S[1, 1] - S[2, 2], S[0, 1] + S[1, 0], S[2, 0] + S[0, 2]],
+                      [S[2, 0] - S[0, 2], S[0, 1] + S[1, 0], -S[0, 0] + S[1, 1] - S[2, 2], S[1, 2] + S[2, 1]],
+                      [S[0, 1] - S[1, 0], S[2, 0] + S[0, 2], S[1, 2] + S[2, 1], -S[0, 0] - S[1, 1] + S[2, 2]]])
+        ev, V = np.linalg.eigh(N)
+        w, x, y, z = V[:, -1]
+        Rq = np.array([[w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                       [2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)],
+                       [2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z]])
+        assert np.allclose(orc.ls_rotation(P, Q, np.ones(40, bool)), Rq, atol=1e-10)
+
+
+def test_ls_rotation_uses_only_the_set(orc):
+    rng = np.random.default_rng(8)
+    R = _random_rotation(rng)
+    P = rng.uniform(-1, 1, (3, 60))
+    Q = R @ P
+    Q[:, 40:] = rng.uniform(-1, 1, (3, 20))     # outliers outside the set
+    m = np.zeros(60, bool)
+    m[:40] = True
+    assert np.allclose(orc.ls_rotation(P, Q, m), R, atol=1e-12)
+    assert orc.ls_rotation(P, Q, np.array([1, 1] + [0] * 58, bool)) is None
