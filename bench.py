@@ -105,9 +105,11 @@ def bench_topk(aor, synth, torch, reps: int) -> dict:
     dt = (time.perf_counter() - t0) / reps
     # each ground-truth rotation against the closest estimate
     errs = [round(min(rotation_error_deg(Rg, o["R"]) for o in outs), 4) for Rg in inst.R_gt]
+    errs_ls = [round(min(rotation_error_deg(Rg, o["R_ls"]) for o in outs), 5) for Rg in inst.R_gt]
     return {"workload": "n=1e6, 3 rotations x 10% inliers, 70% outliers, top-3, NMS 5, G=1024 + 64x64, B=3600",
             "found": len(outs), "ms_per_solve": round(dt * 1e3, 3), "Mcorr_s": round(n / dt / 1e6, 2),
-            "rotation_error_deg": errs, "inliers": [int(o["n_inliers"]) for o in outs]}
+            "rotation_error_deg": errs, "rotation_error_deg_ls": errs_ls,
+            "inliers": [int(o["n_inliers"]) for o in outs]}
 
 
 def bench_batch(aor, synth, torch, reps: int) -> dict:
@@ -251,6 +253,7 @@ def main() -> int:
     # accuracy of the measured path on this input (mask kept on device)
     res, mask, st = aor.est_rotation(P, Q, prm)
     re_gpu = rotation_error_deg(inst.R_gt[0], res["R"])
+    re_ls = rotation_error_deg(inst.R_gt[0], res["R_ls"])
 
     for _ in range(args.warmup):
         aor.est_rotation(P, Q, prm)
@@ -320,6 +323,7 @@ def main() -> int:
         "batch": bench_batch(aor, synth, torch, args.batch_reps) if args.batch_reps > 0 else None,
         "serve": bench_serve(aor, synth, args.serve_seconds) if args.serve_seconds > 0 else None,
         "rotation_error_deg": round(re_gpu, 4),
+        "rotation_error_deg_ls": round(re_ls, 5),
         "status": int(st),
         "n_inliers": res["n_inliers"],
     }

@@ -79,6 +79,8 @@ typedef struct {
     uint32_t fine_votes;     /* votes of the refined peak */
     uint32_t angle_votes;    /* votes of the angle bin */
     uint32_t n_inliers;      /* number of i with ||R p_i - q_i|| <= tau */
+    float R_ls[9];           /* least-squares rotation on that inlier set (float64 accumulation and solve,
+                                rounded); equals R when there are fewer than three inliers */
 } aoresp_result;
 
 /* Grid resolution chosen for n when params.grid == 0: a pure function of n

@@ -36,7 +36,7 @@ class Result(C.Structure):
     _fields_ = [("R", C.c_float * 9), ("axis", C.c_float * 3), ("angle", C.c_float),
                 ("grid", C.c_uint32), ("peak_cell", C.c_uint32), ("fine_cell", C.c_uint32),
                 ("angle_bin", C.c_uint32), ("axis_votes", C.c_uint32), ("fine_votes", C.c_uint32),
-                ("angle_votes", C.c_uint32), ("n_inliers", C.c_uint32)]
+                ("angle_votes", C.c_uint32), ("n_inliers", C.c_uint32), ("R_ls", C.c_float * 9)]
 
     def todict(self) -> dict:
         return {
@@ -47,6 +47,7 @@ class Result(C.Structure):
             "angle_bin": int(self.angle_bin), "axis_votes": int(self.axis_votes),
             "fine_votes": int(self.fine_votes), "angle_votes": int(self.angle_votes),
             "n_inliers": int(self.n_inliers),
+            "R_ls": np.array(self.R_ls[:], dtype=np.float32).reshape(3, 3),
         }
 
 

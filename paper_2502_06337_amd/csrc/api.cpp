@@ -232,6 +232,8 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         plan.fine_cells += (size_t)I.npk * rp.M * rp.M;
         I.hist_off = (int64_t)plan.hist_cells;
         plan.hist_cells += (size_t)I.npk * rp.B;
+        I.item0 = (int32_t)plan.corr_items.size();
+        I.nitems = 0;
         const AngleTables* at = angle_tables(ctx, rp.B);
         const int16_t* disk = disk_table(ctx, rp.G);
         if (!at || !disk) return AORESP_ENOMEM;
@@ -275,6 +277,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
             int64_t i1 = i0 + kCorrChunk < n ? i0 + kCorrChunk : n;
             plan.corr_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
         }
+        I.nitems = (int)plan.corr_items.size() - I.item0;
         if (rp.M > 0)
             for (int64_t i0 = 0; i0 < n; i0 += kListChunk) {
                 int64_t i1 = i0 + kListChunk < n ? i0 + kListChunk : n;
@@ -320,6 +323,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     const OutLayout ol(plan.nres);
     if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
     if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
+    if ((st = w.lsum.ensure((plan.corr_items.size() + 1) * kLsWords * sizeof(double))) != AORESP_OK) return st;
     if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
@@ -394,6 +398,10 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     for (int t = 0; t < plan.max_npk; ++t) launch_angle_peak(w.hist.as<uint32_t>(), insts, ninst, stt, t, res, s);
     mark(5);
     launch_inliers(P, Q, N, insts, ninst, stt, res, plan.nres, masks, w.icount.as<uint32_t>(), s);
+    for (int t = 0; t < plan.max_npk; ++t) {
+        launch_ls_accum(P, Q, N, insts, corr_items, (int)plan.corr_items.size(), stt, res, t, w.lsum.as<double>(), s);
+        launch_ls_finish(insts, ninst, w.lsum.as<double>(), stt, res, t, s);
+    }
     mark(6);
     if (ninst == 1) {
         const Inst& I = plan.insts[0];
@@ -501,6 +509,7 @@ aoresp_status reserve_plan(Workspace& w, const Plan& plan) {
     const OutLayout ol(plan.nres);
     if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
     if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
+    if ((st = w.lsum.ensure((plan.corr_items.size() + 1) * kLsWords * sizeof(double))) != AORESP_OK) return st;
     if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
     const size_t total = plan_blob_bytes(plan);
     if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
@@ -514,7 +523,7 @@ void release_workspace(Workspace& w) {
     if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
     w.cap_stream = nullptr;
     DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.out,
-                      &w.icount, &w.plan, &w.P, &w.Q, &w.masks};
+                      &w.icount, &w.lsum, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
     HostBuf* hb[] = {&w.h_plan, &w.h_out};
     for (HostBuf* b : hb) {
@@ -524,9 +533,10 @@ void release_workspace(Workspace& w) {
     }
 }
 
-static void identity_result(aoresp_result* r, int G) {
+void identity_result(aoresp_result* r, int G) {
     std::memset(r, 0, sizeof(*r));
     r->R[0] = r->R[4] = r->R[8] = 1.0f;
+    r->R_ls[0] = r->R_ls[4] = r->R_ls[8] = 1.0f;
     r->grid = (uint32_t)G;
 }
 

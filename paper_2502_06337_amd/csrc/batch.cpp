@@ -68,10 +68,7 @@ static aoresp_status batch_common(const float* P, const float* Q, const uint64_t
     // instances with fewer than two correspondences or no vote: R = I
     for (uint32_t b = 0; b < batch; ++b) {
         if (off[b + 1] - off[b] < 2 || !valid[b]) {
-            uint32_t G = (uint32_t)rps[b].G;
-            std::memset(&out[b], 0, sizeof(aoresp_result));
-            out[b].R[0] = out[b].R[4] = out[b].R[8] = 1.0f;
-            out[b].grid = G;
+            identity_result(&out[b], rps[b].G);
         }
     }
     return AORESP_OK;

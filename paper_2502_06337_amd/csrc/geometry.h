@@ -107,6 +107,137 @@ AOR_HD __forceinline__ float cross_root_f(float a, float b, float c, float x, in
     return K * seed_rcp(qq);
 }
 
+// Eigenvector of the largest eigenvalue of a symmetric 4x4 matrix, by cyclic
+// Jacobi rotations (each annihilates one off-diagonal pair; the accumulated
+// rotations hold the eigenvectors).
+AOR_HD inline void top_eigvec4(double A[4][4], double out[4]) {
+    double V[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 32; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < 4; ++i) {
+            diag += A[i][i] * A[i][i];
+            for (int j = i + 1; j < 4; ++j) off += A[i][j] * A[i][j];
+        }
+        if (!(off > 1e-32 * diag)) break;
+        for (int p = 0; p < 3; ++p)
+            for (int q = p + 1; q < 4; ++q) {
+                const double apq = A[p][q];
+                if (apq == 0.0) continue;
+                const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                A[p][p] -= t * apq;
+                A[q][q] += t * apq;
+                A[p][q] = A[q][p] = 0.0;
+                for (int r = 0; r < 4; ++r) {
+                    if (r != p && r != q) {
+                        const double arp = A[r][p], arq = A[r][q];
+                        A[r][p] = A[p][r] = c * arp - sn * arq;
+                        A[r][q] = A[q][r] = sn * arp + c * arq;
+                    }
+                    const double vrp = V[r][p], vrq = V[r][q];
+                    V[r][p] = c * vrp - sn * vrq;
+                    V[r][q] = sn * vrp + c * vrq;
+                }
+            }
+    }
+    int best = 0;
+    for (int i = 1; i < 4; ++i)
+        if (A[i][i] > A[best][best]) best = i;
+    for (int i = 0; i < 4; ++i) out[i] = V[i][best];
+}
+
+// Determinant of the 3x3 matrix left by removing row r and column c of a 4x4.
+AOR_HD inline double minor3(const double M[4][4], int r, int c) {
+    int ri[3], ci[3];
+    for (int k = 0, a = 0, b = 0; k < 4; ++k) {
+        if (k != r) ri[a++] = k;
+        if (k != c) ci[b++] = k;
+    }
+    const double* m0 = M[ri[0]];
+    const double* m1 = M[ri[1]];
+    const double* m2 = M[ri[2]];
+    return m0[ci[0]] * (m1[ci[1]] * m2[ci[2]] - m1[ci[2]] * m2[ci[1]]) -
+           m0[ci[1]] * (m1[ci[0]] * m2[ci[2]] - m1[ci[2]] * m2[ci[0]]) +
+           m0[ci[2]] * (m1[ci[0]] * m2[ci[1]] - m1[ci[1]] * m2[ci[0]]);
+}
+
+// Eigenvector of the largest eigenvalue of a symmetric trace-free 4x4 matrix
+// N: the eigenvalue by Newton's method on the characteristic polynomial
+// lambda^4 + c2 lambda^2 + c1 lambda + c0 (c2 = -tr(N^2)/2, c1 = -tr(N^3)/3,
+// c0 = det N), started at sqrt(tr(N^2)) >= lambda_max, where the iteration
+// decreases monotonically (all roots are real); the eigenvector is a column of
+// the adjugate of N - lambda I, the one with the largest diagonal entry.
+// Returns false when that column is too small for a clean direction (a
+// near-repeated top eigenvalue); the caller then uses the Jacobi rotations.
+AOR_HD inline bool top_eigvec4_newton(const double N[4][4], double out[4]) {
+    double N2[4][4];
+    double tr2 = 0.0, tr3 = 0.0;
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 4; ++k) acc += N[i][k] * N[k][j];
+            N2[i][j] = acc;
+            tr2 += N[i][j] * N[i][j];
+        }
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) tr3 += N2[i][j] * N[j][i];
+    if (!(tr2 > 0.0)) return false;
+    double detN = 0.0;
+    for (int j = 0; j < 4; ++j) detN += ((j & 1) ? -1.0 : 1.0) * N[0][j] * minor3(N, 0, j);
+    const double c2 = -0.5 * tr2, c1 = -tr3 / 3.0, c0 = detN;
+    double lam = sqrt(tr2);
+    for (int it = 0; it < 100; ++it) {
+        const double l2 = lam * lam;
+        const double f = ((l2 + c2) * lam + c1) * lam + c0;
+        const double fp = (4.0 * l2 + 2.0 * c2) * lam + c1;
+        if (!(fp > 0.0)) break;
+        const double step = f / fp;
+        lam -= step;
+        if (!(fabs(step) > 1e-15 * fabs(lam))) break;
+    }
+    double M[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) M[i][j] = N[i][j] - (i == j ? lam : 0.0);
+    int best = 0;
+    double dbest = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        const double d = fabs(minor3(M, i, i));
+        if (d > dbest) {
+            dbest = d;
+            best = i;
+        }
+    }
+    // a simple top eigenvalue leaves adj(M) = mu v v^T with |mu| about the
+    // product of the other three eigenvalue gaps; demand a clear margin
+    if (!(dbest > 1e-12 * tr2 * sqrt(tr2))) return false;
+    for (int j = 0; j < 4; ++j) out[j] = (((best + j) & 1) ? -1.0 : 1.0) * minor3(M, best, j);
+    return true;
+}
+
+// Rotation maximising sum q_i . (R p_i) from the sums S[3a + b] = sum p_a q_b
+// (equivalently minimising sum ||R p_i - q_i||^2): the unit quaternion
+// (w, x, y, z) is the top eigenvector of the symmetric 4x4 matrix N built from
+// S (the quaternion method of least-squares registration), then R from the
+// quaternion; float64 throughout, rounded once.
+AOR_HD inline void ls_rotation_from_sums(const double* S, float* R) {
+    double N4[4][4] = {
+        {S[0] + S[4] + S[8], S[5] - S[7], S[6] - S[2], S[1] - S[3]},
+        {S[5] - S[7], S[0] - S[4] - S[8], S[1] + S[3], S[6] + S[2]},
+        {S[6] - S[2], S[1] + S[3], -S[0] + S[4] - S[8], S[5] + S[7]},
+        {S[1] - S[3], S[6] + S[2], S[5] + S[7], -S[0] - S[4] + S[8]}};
+    double qv[4];
+    if (!top_eigvec4_newton(N4, qv)) top_eigvec4(N4, qv);
+    const double nq = sqrt(qv[0] * qv[0] + qv[1] * qv[1] + qv[2] * qv[2] + qv[3] * qv[3]);
+    const double w = qv[0] / nq, x = qv[1] / nq, y = qv[2] / nq, z = qv[3] / nq;
+    const double Rd[9] = {w * w + x * x - y * y - z * z, 2.0 * (x * y - w * z), 2.0 * (x * z + w * y),
+                          2.0 * (x * y + w * z), w * w - x * x + y * y - z * z, 2.0 * (y * z - w * x),
+                          2.0 * (x * z - w * y), 2.0 * (y * z + w * x), w * w - x * x - y * y + z * z};
+    for (int k = 0; k < 9; ++k) R[k] = (float)Rd[k];
+}
+
 AOR_HD __forceinline__ int32_t pack_range(int s, int e) {
     return (int32_t)((uint32_t)(uint16_t)(int16_t)s | ((uint32_t)(uint16_t)(int16_t)e << 16));
 }

@@ -57,6 +57,7 @@ struct Inst {
     int64_t grid_off;     // u32 offset of its G*G coarse grid in the grid arena
     int64_t fine_off;     // u32 offset of its npk fine grids (M*M each)
     int64_t hist_off;     // u32 offset of its npk histograms (B each)
+    int32_t item0, nitems;   // its correspondence items (first index, count)
     const int16_t* disk;  // in-disk cross range per cell line (G pairs)
     const float* tc;      // angle tables for B: boundary cos / sin, centre angle / cos / sin
     const float* ts;
@@ -122,6 +123,15 @@ void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* in
                        const PeakState* st, uint32_t* hist_arena, size_t lds_bytes, hipStream_t s);
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                        aoresp_result* res, hipStream_t s);
+// Least-squares rotation on the inlier set of result slot `slot`: per
+// correspondence item, the float64 sums of p q^T over the inliers and their
+// count (kLsWords doubles per item, in partial); then per instance the sums of
+// its items in a fixed order and the rotation (res[..].R_ls).
+constexpr int kLsWords = 10;
+void launch_ls_accum(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
+                     const PeakState* st, const aoresp_result* res, int slot, double* partial, hipStream_t s);
+void launch_ls_finish(const Inst* insts, int ninst, const double* partial, const PeakState* st, aoresp_result* res,
+                      int slot, hipStream_t s);
 // partial: nres * kCountSlots counters, zero on entry.
 void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, const PeakState* st,
                     aoresp_result* res, int nres, uint8_t* masks, uint32_t* partial, hipStream_t s);

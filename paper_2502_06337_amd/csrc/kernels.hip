@@ -949,6 +949,23 @@ __global__ __launch_bounds__(1024) void k_angle_peak(const uint32_t* __restrict_
 // that no single address takes one atomic per block; k_inliers_total sums
 // the partials into the result.  Blocks that straddle two instances add per
 // correspondence straight into the result.
+// Squared residual ||R p - q||^2 of Eq. (1) in binary32, in the fixed order
+// that decides inlier membership everywhere (mask, count, least squares).
+__device__ __forceinline__ float residual2(const float* R, float p0, float p1, float p2, const float* qv) {
+    float e[3];
+    for (int j = 0; j < 3; ++j) {
+        float t0 = R[j * 3 + 0] * p0;
+        float t1 = R[j * 3 + 1] * p1;
+        float t2 = R[j * 3 + 2] * p2;
+        float sm = (t0 + t1) + t2;
+        e[j] = sm - qv[j];
+    }
+    float e0 = e[0] * e[0];
+    float e1 = e[1] * e[1];
+    float e2 = e[2] * e[2];
+    return (e0 + e1) + e2;
+}
+
 // One block per kInlierSub x 256 consecutive columns: the columns' inputs
 // are loaded first, then each is tested against every peak of its instance.
 constexpr int kInlierSub = 4;
@@ -986,22 +1003,8 @@ __global__ __launch_bounds__(256) void k_inliers(const float* __restrict__ P, co
             bool act = live && t < I.npk;
             if (!block_uniform && !__any(act)) break;
             uint8_t m = 0;
-            if (act && I.n >= 2 && st[I.res_off + t].valid) {
-                const float* R = res[I.res_off + t].R;
-                float e[3];
-                for (int j = 0; j < 3; ++j) {
-                    float t0 = R[j * 3 + 0] * pv[u][0];
-                    float t1 = R[j * 3 + 1] * pv[u][1];
-                    float t2 = R[j * 3 + 2] * pv[u][2];
-                    float sm = (t0 + t1) + t2;
-                    e[j] = sm - qv[u][j];
-                }
-                float e0 = e[0] * e[0];
-                float e1 = e[1] * e[1];
-                float e2 = e[2] * e[2];
-                float res2 = (e0 + e1) + e2;
-                m = res2 <= tt ? 1 : 0;
-            }
+            if (act && I.n >= 2 && st[I.res_off + t].valid)
+                m = residual2(res[I.res_off + t].R, pv[u][0], pv[u][1], pv[u][2], qv[u]) <= tt ? 1 : 0;
             if (act && masks) masks[(size_t)t * N + i] = m;
             if (block_uniform) {
                 unsigned long long bal = __ballot(m != 0);
@@ -1026,6 +1029,76 @@ __global__ void k_inliers_total(const uint32_t* __restrict__ partial, int nres, 
     uint32_t sum = 0u;
     for (int k = 0; k < kCountSlots; ++k) sum += partial[(size_t)r * kCountSlots + k];
     res[r].n_inliers += sum;
+}
+
+// --------------------------------------------------------------------------
+// Least-squares rotation on the inlier set
+// --------------------------------------------------------------------------
+
+// Sum of kLsWords doubles over a 256-thread block, in a fixed order.
+__device__ __forceinline__ void block_sum_ls(double* v, double (*red)[256]) {
+    const int t = threadIdx.x;
+    for (int k = 0; k < kLsWords; ++k) red[k][t] = v[k];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h)
+            for (int k = 0; k < kLsWords; ++k) red[k][t] += red[k][t + h];
+        __syncthreads();
+    }
+    for (int k = 0; k < kLsWords; ++k) v[k] = red[k][0];
+}
+
+// Per correspondence item: S_ab = sum p_a q_b over the inliers of slot `slot`
+// (the residual test of the inlier mask), and their count; each thread sums
+// its columns in order, then the block in a fixed tree.
+__global__ __launch_bounds__(256) void k_ls_accum(const float* __restrict__ P, const float* __restrict__ Q,
+                                                  int64_t N, const Inst* __restrict__ insts,
+                                                  const int4* __restrict__ items, const PeakState* st,
+                                                  const aoresp_result* res, int slot, double* __restrict__ partial) {
+    __shared__ double red[kLsWords][256];
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
+    double acc[kLsWords];
+    for (int k = 0; k < kLsWords; ++k) acc[k] = 0.0;
+    if (slot < I.npk && I.n >= 2 && st[I.res_off + slot].valid) {
+        float R[9];
+        for (int k = 0; k < 9; ++k) R[k] = res[I.res_off + slot].R[k];
+        const float tt = I.tau * I.tau;
+        for (int64_t li = wi.y + threadIdx.x; li < wi.z; li += blockDim.x) {
+            const int64_t i = I.off + li;
+            const float p0 = P[i], p1 = P[N + i], p2 = P[2 * N + i];
+            const float qv[3] = {Q[i], Q[N + i], Q[2 * N + i]};
+            if (!(residual2(R, p0, p1, p2, qv) <= tt)) continue;
+            const double pd[3] = {p0, p1, p2};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) acc[3 * a + b] += pd[a] * (double)qv[b];
+            acc[9] += 1.0;
+        }
+    }
+    block_sum_ls(acc, red);
+    if (threadIdx.x < kLsWords) partial[(size_t)blockIdx.x * kLsWords + threadIdx.x] = acc[threadIdx.x];
+}
+
+// Per instance: the sums of its items in a fixed order, then the rotation
+// (ls_rotation_from_sums).  Fewer than three inliers (or an invalid peak):
+// R_ls = R.
+__global__ __launch_bounds__(256) void k_ls_finish(const Inst* __restrict__ insts, const double* __restrict__ partial,
+                                                   const PeakState* st, aoresp_result* res, int slot) {
+    __shared__ double red[kLsWords][256];
+    const Inst& I = insts[blockIdx.x];
+    if (slot >= I.npk) return;
+    double acc[kLsWords];
+    for (int k = 0; k < kLsWords; ++k) acc[k] = 0.0;
+    for (int it = threadIdx.x; it < I.nitems; it += blockDim.x)
+        for (int k = 0; k < kLsWords; ++k) acc[k] += partial[(size_t)(I.item0 + it) * kLsWords + k];
+    block_sum_ls(acc, red);
+    if (threadIdx.x != 0) return;
+    aoresp_result& o = res[I.res_off + slot];
+    if (!st[I.res_off + slot].valid || I.n < 2 || acc[9] < 3.0) {
+        for (int k = 0; k < 9; ++k) o.R_ls[k] = o.R[k];
+        return;
+    }
+    ls_rotation_from_sums(acc, o.R_ls);
 }
 
 __global__ void k_zero_u32(uint32_t* p, size_t count) {
@@ -1132,6 +1205,19 @@ void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* in
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                        aoresp_result* res, hipStream_t s) {
     hipLaunchKernelGGL(k_angle_peak, dim3((unsigned)ninst), dim3(1024), 0, s, hist_arena, insts, st, slot, res);
+}
+
+void launch_ls_accum(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
+                     const PeakState* st, const aoresp_result* res, int slot, double* partial, hipStream_t s) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(k_ls_accum, dim3((unsigned)nitems), dim3(256), 0, s, P, Q, N, insts, items, st, res, slot,
+                       partial);
+}
+
+void launch_ls_finish(const Inst* insts, int ninst, const double* partial, const PeakState* st, aoresp_result* res,
+                      int slot, hipStream_t s) {
+    if (ninst <= 0) return;
+    hipLaunchKernelGGL(k_ls_finish, dim3((unsigned)ninst), dim3(256), 0, s, insts, partial, st, res, slot);
 }
 
 void launch_inliers(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, const PeakState* st,

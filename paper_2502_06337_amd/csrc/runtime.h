@@ -68,6 +68,7 @@ struct Workspace {
     DevBuf keys;                    // per result slot: peak search keys
     DevBuf out;                     // results, peak states, flag and counter (OutLayout)
     DevBuf icount;                  // partial inlier counters (kCountSlots per result slot)
+    DevBuf lsum;                    // least-squares sums per correspondence item (kLsWords doubles)
     DevBuf plan;                    // instance table + work items
     DevBuf P, Q, masks;             // staging for host-pointer entry points
     HostBuf h_plan, h_out;          // pinned mirrors
@@ -137,6 +138,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
 // Enqueue the copy of the nres results (and the check flag) into w's pinned
 // mirrors; collect_plan reads them after the stream has been synchronised.
 aoresp_status fetch_plan(Workspace& w, const Plan& plan, hipStream_t s);
+// R = R_ls = I, zero counts, grid G: the result of a solve without data.
+void identity_result(aoresp_result* r, int G);
 aoresp_status collect_plan(Workspace& w, const Plan& plan, aoresp_result* out, std::vector<int>& valid);
 // fetch + synchronise + collect.
 aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, std::vector<int>& valid,

@@ -239,9 +239,7 @@ struct aoresp_server {
             r->mask.assign(hm + o, hm + o + r->n);
             aoresp_status rs = AORESP_OK;
             if (r->n < 2 || !valid[b]) {
-                std::memset(&r->result, 0, sizeof(aoresp_result));
-                r->result.R[0] = r->result.R[4] = r->result.R[8] = 1.0f;
-                r->result.grid = (uint32_t)r->rp.G;
+                identity_result(&r->result, r->rp.G);
                 std::fill(r->mask.begin(), r->mask.end(), 0);
                 rs = AORESP_ENODATA;
             }

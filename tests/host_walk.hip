@@ -251,4 +251,8 @@ int hw_fine_grid(const float* P, const float* Q, long n, float U0, float V0, flo
     return (int)bad;
 }
 
+// Least-squares rotation from the sums S[3a + b] = sum p_a q_b (the library's
+// quaternion solve, host build).
+void hw_ls_rotation(const double* S, float* R) { ls_rotation_from_sums(S, R); }
+
 }  // extern "C"

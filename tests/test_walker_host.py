@@ -126,3 +126,27 @@ def test_certificate_audit_at_scale(hw, G):
     assert bad == 0
     assert audit[0] > (1e8 if G == 1024 else 5e6)
     assert audit[1] == 0
+
+
+def test_ls_rotation_solve_matches_oracle(hw, orc):
+    """The library's quaternion solve (host build) against the oracle's SVD
+    solve on the same float64 sums: equal to a few float32 rounding steps."""
+    hw.hw_ls_rotation.restype = None
+    hw.hw_ls_rotation.argtypes = [C.c_void_p, C.c_void_p]
+    rng = np.random.default_rng(21)
+    for trial in range(200):
+        q = rng.normal(size=4)
+        q /= np.linalg.norm(q)
+        w, x, y, z = q
+        R = np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                      [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                      [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+        n = int(rng.integers(3, 200))
+        P = rng.uniform(-1, 1, (3, n)).astype(np.float32)
+        Q = (R @ P + rng.uniform(0.0, 0.05) * rng.normal(size=(3, n))).astype(np.float32)
+        m = np.ones(n, bool)
+        S = np.ascontiguousarray((P.astype(np.float64) @ Q.astype(np.float64).T).ravel())
+        out = np.zeros(9, np.float32)
+        hw.hw_ls_rotation(S.ctypes.data, out.ctypes.data)
+        ref = orc.ls_rotation(P, Q, m)
+        assert np.max(np.abs(out.reshape(3, 3).astype(np.float64) - ref)) <= 2.0 ** -22, trial
