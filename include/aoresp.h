@@ -133,7 +133,8 @@ aoresp_status aoresp_solve_debug_dev(const float* P, const float* Q, size_t n, c
  * ms_out receives *n_stages durations in milliseconds, in this order: setup
  * (per-correspondence records, zeroing), coarse vote, peak search,
  * refinement (fine vote, fine peak, axis), angle histogram and rotation,
- * inlier mask.  For measurement; results are discarded. */
+ * inlier mask and least-squares rotation.  For measurement; results are
+ * discarded. */
 aoresp_status aoresp_stage_times_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
                                      float* ms_out, uint32_t* n_stages, void* hip_stream);
 

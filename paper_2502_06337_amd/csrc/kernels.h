@@ -111,10 +111,10 @@ void launch_peak(const uint32_t* grid_arena, const Inst* insts, const int4* item
                  int slot, unsigned long long* keys, hipStream_t s);
 void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* keys, PeakState* st, int slot,
                         hipStream_t s);
-// correspondence items: int4 (inst, i0, i1, -); one block each.  The fine
-// vote runs in two passes: the filter lists the correspondences whose curve
-// may cross the window (list: one int32 per global column, counts: one per
-// instance, zero on entry); the vote items index positions of that list.
+// correspondence items: int4 (inst, i0, i1, -); one block each.  A block
+// lists the correspondences of its range whose curve may cross the window of
+// result slot `slot`, builds their pieces in the window frame, walks them into
+// an LDS tile and adds the tile to that slot's fine grid.
 void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, const PeakState* st, int slot,
                       uint32_t* fine_arena, uint32_t* err, int maxM, hipStream_t s);
 void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, PeakState* st, int slot,

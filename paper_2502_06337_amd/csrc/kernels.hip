@@ -15,6 +15,9 @@
 //                    (Sec. IV-B, Eq. (10))
 //   k_angle_peak     histogram peak, Rodrigues rotation (Eq. (2))
 //   k_inliers        residual mask against Eq. (1)
+//   k_ls_accum       float64 sums of p q^T over the inliers, per item
+//   k_ls_finish      least-squares rotation on the inlier set (quaternion
+//                    method; a refinement after Eq. (1), not in the paper)
 // Nothing here is a dense contraction: the vote kernels are bound by VALU
 // work per vote and LDS atomics, the rest by HBM streaming.
 #include <hip/hip_runtime.h>
