@@ -88,6 +88,7 @@ def lib():
             "or_coarse_cell": (C.c_uint32, [_fp, _fp, C.c_long, C.c_int, C.c_int, C.c_int]),
             "or_arc_votes": (C.c_long, [_fp, _fp, C.c_int]),
             "or_argmax": (C.c_uint32, [_u32p, C.c_long, _lp]),
+            "or_window_gate": (None, [_fp, _fp, C.c_long, C.c_int, C.c_int, C.c_int, C.c_int, _u8p]),
             "or_fine_window": (None, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Window)]),
             "or_fine_grid": (None, [_fp, _fp, C.c_long, C.POINTER(Window), _u32p]),
             "or_fine_cell": (C.c_uint32, [_fp, _fp, C.c_long, C.POINTER(Window), C.c_int, C.c_int]),
@@ -260,6 +261,45 @@ def rotation_error_deg(Rgt, R) -> float:
     Rgt = np.ascontiguousarray(Rgt, dtype=np.float64).ravel()
     R = _f32(R).ravel()
     return float(lib().or_rotation_error_deg(Rgt.ctypes.data_as(C.POINTER(C.c_double)), _ptr(R, _fp)))
+
+
+def window_gate(P, Q, G: int, peak_cell: int, w: int) -> np.ndarray:
+    """Correspondences whose curve votes for a cell of the (2w+1)^2 window of
+    coarse cells around the peak (clipped), by the per-cell rule."""
+    P, Q = _f32(P), _f32(Q)
+    g = np.zeros(P.shape[1], dtype=np.uint8)
+    lib().or_window_gate(_ptr(P, _fp), _ptr(Q, _fp), P.shape[1], G, peak_cell % G, peak_cell // G, w,
+                         _ptr(g, _u8p))
+    return g.astype(bool)
+
+
+def angle_coarse_to_fine(P, Q, r, G: int, peak_cell: int, w: int, B: int, F: int, gate: bool = True) -> dict:
+    """Coarse-to-fine angle voting (a variant of Sec. IV-B): only the
+    correspondences that pass the window gate vote (all of them without the
+    gate); the coarse B-bin histogram gives bin k (ties to the lowest bin);
+    with F > 1 a second histogram over the partition of [-pi, pi) into B*F
+    bins, read on the 3F fine bins of coarse bins k-1, k, k+1 (cyclically, in
+    that order; ties to the first), gives the fine bin, and the angle and R
+    come from that bin's centre (Eq. (2)); with F <= 1 from bin k's centre."""
+    P, Q, r = _f32(P), _f32(Q), _f32(r)
+    m = window_gate(P, Q, G, peak_cell, w) if gate else np.ones(P.shape[1], bool)
+    Pg, Qg = np.ascontiguousarray(P[:, m]), np.ascontiguousarray(Q[:, m])
+    h = angle_hist(Pg, Qg, r, B)
+    k = int(np.argmax(h))
+    out = {"gate": m, "hist": h, "angle_bin": k, "angle_votes": int(h[k]),
+           "angle_fine_bin": 0, "angle_fine_votes": 0}
+    if F <= 1:
+        th, ct, st = angle_centers(B)
+        out["angle"], out["R"] = np.float32(th[k]), rotation(r, ct[k], st[k])
+        return out
+    hf = angle_hist(Pg, Qg, r, B * F)
+    win = [((k + dc) % B) * F + j for dc in (-1, 0, 1) for j in range(F)]
+    vals = hf[win]
+    jf = win[int(np.argmax(vals))]
+    th, ct, st = angle_centers(B * F)
+    out.update({"fine_hist": vals, "angle_fine_bin": jf, "angle_fine_votes": int(hf[jf]),
+                "angle": np.float32(th[jf]), "R": rotation(r, ct[jf], st[jf])})
+    return out
 
 
 def ls_rotation(P, Q, mask) -> np.ndarray:

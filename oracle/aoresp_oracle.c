@@ -175,6 +175,24 @@ OR_EXPORT uint32_t or_coarse_cell(const float* P, const float* Q, long n, int G,
     return cnt;
 }
 
+/* Angle-vote gate (coarse-to-fine angle voting, a variant of Sec. IV-B):
+ * gate[i] = 1 iff correspondence i votes for at least one cell of the
+ * (2w+1)^2 window of coarse cells centred on cell (px, py), clipped to the
+ * grid (the per-cell rule of Sec. IV-A). */
+OR_EXPORT void or_window_gate(const float* P, const float* Q, long n, int G, int px, int py, int w, uint8_t* gate) {
+    int x0 = px - w < 0 ? 0 : px - w, x1 = px + w > G - 1 ? G - 1 : px + w;
+    int y0 = py - w < 0 ? 0 : py - w, y1 = py + w > G - 1 ? G - 1 : py + w;
+    for (long i = 0; i < n; ++i) {
+        float p[3], q[3];
+        gather(P, n, i, p);
+        gather(Q, n, i, q);
+        int g = 0;
+        for (int iy = y0; iy <= y1 && !g; ++iy)
+            for (int ix = x0; ix <= x1 && !g; ++ix) g = or_coarse_hit(p, q, G, ix, iy);
+        gate[i] = (uint8_t)g;
+    }
+}
+
 /* Number of coarse cells one correspondence votes for (brute force). */
 OR_EXPORT long or_arc_votes(const float* p, const float* q, int G) {
     long cnt = 0;

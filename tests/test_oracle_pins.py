@@ -517,3 +517,70 @@ def test_ls_rotation_uses_only_the_set(orc):
     m[:40] = True
     assert np.allclose(orc.ls_rotation(P, Q, m), R, atol=1e-12)
     assert orc.ls_rotation(P, Q, np.array([1, 1] + [0] * 58, bool)) is None
+
+
+# --------------------------------------------- coarse-to-fine angle voting
+def test_window_gate_matches_per_cell_votes(orc):
+    """A correspondence passes the gate iff its single-correspondence grid has
+    a vote inside the window (clipped at the grid edge)."""
+    G, w = 64, 1
+    inst = synth.make_instance(120, 41)
+    for peak in (33 * G + 17, 0, G * G - 1, 5 * G + 63):
+        g = orc.window_gate(inst.P, inst.Q, G, peak, w)
+        px, py = peak % G, peak // G
+        for i in range(inst.n):
+            grid = orc.coarse_grid(inst.P[:, i:i + 1], inst.Q[:, i:i + 1], G)
+            sub = grid[max(0, py - w):py + w + 1, max(0, px - w):px + w + 1]
+            assert bool(g[i]) == bool(sub.sum() > 0), (peak, i)
+
+
+def test_window_gate_keeps_exact_inliers(orc):
+    """Noise-free correspondences of a rotation about r all vote for the cell
+    containing the projection of r (their great circles pass through r)."""
+    rng = np.random.default_rng(12)
+    G = 256
+    for _ in range(5):
+        r = rng.normal(size=3)
+        r /= np.linalg.norm(r)
+        if r[2] > 0:
+            r = -r
+        u, v = r[0] / (1 - r[2]), r[1] / (1 - r[2])
+        ix, iy = int((u + 1) * G / 2), int((v + 1) * G / 2)
+        K = np.array([[0, -r[2], r[1]], [r[2], 0, -r[0]], [-r[1], r[0], 0]])
+        R = np.eye(3) + math.sin(0.9) * K + (1 - math.cos(0.9)) * K @ K
+        P = rng.uniform(-1, 1, (3, 200)).astype(np.float32)
+        Q = (R @ P.astype(np.float64)).astype(np.float32)
+        assert orc.window_gate(P, Q, G, iy * G + ix, 1).all()
+
+
+def test_angle_coarse_to_fine_consistency_and_accuracy(orc):
+    """Without the gate and with F = 1 it is the solve's angle step; on
+    noise-free data about the exact axis the refined angle lies within half a
+    fine bin of the generating angle (and inside the coarse window)."""
+    inst = synth.make_instance(1500, 43)
+    G, B = 128, 360
+    r_or = orc.solve(inst.P, inst.Q, G=G, B=B)
+    out = orc.angle_coarse_to_fine(inst.P, inst.Q, r_or["axis"], G, r_or["peak_cell"], 1, B, 1, gate=False)
+    assert out["angle_bin"] == r_or["angle_bin"] and out["angle_votes"] == r_or["angle_votes"]
+    assert np.array_equal(out["R"].view(np.uint32), r_or["R"].view(np.uint32))
+    rng = np.random.default_rng(44)
+    B, F = 360, 16
+    for _ in range(6):
+        r = rng.normal(size=3)
+        r /= np.linalg.norm(r)
+        if r[2] > 0:
+            r = -r
+        theta = float(rng.uniform(-math.pi, math.pi))
+        K = np.array([[0, -r[2], r[1]], [r[2], 0, -r[0]], [-r[1], r[0], 0]])
+        R = np.eye(3) + math.sin(theta) * K + (1 - math.cos(theta)) * K @ K
+        P = rng.uniform(-1, 1, (3, 400)).astype(np.float32)
+        Q = (R @ P.astype(np.float64)).astype(np.float32)
+        Q[:, 200:] = rng.uniform(-1, 1, (3, 200)).astype(np.float32)
+        u, v = r[0] / (1 - r[2]), r[1] / (1 - r[2])
+        ix, iy = int((u + 1) * G / 2), int((v + 1) * G / 2)
+        out = orc.angle_coarse_to_fine(P, Q, r.astype(np.float32), G, iy * G + ix, 1, B, F)
+        half = math.pi / (B * F)
+        d = abs((float(out["angle"]) - theta + math.pi) % (2 * math.pi) - math.pi)
+        assert d <= half * 1.01, (d, half)
+        assert out["angle_fine_bin"] // F in {(out["angle_bin"] + dc) % B for dc in (-1, 0, 1)}
+        assert out["angle_fine_votes"] >= 200 and out["gate"][:200].all()
