@@ -64,6 +64,12 @@ typedef struct {
     uint32_t angle_bins;     /* B: bins over [-pi, pi); 0 -> 360; at most 8192 */
     uint32_t nms_radius;     /* top-k suppression radius in coarse cells; 0 -> 5 */
     float inlier_thresh;     /* tau on ||R p - q||; <= 0 -> 0.05 */
+    uint32_t angle_gate;     /* 1: only correspondences that vote for a coarse cell of the (2w+1)^2 window
+                                around the peak (w = refine_halfwin, clipped; the per-cell rule of
+                                Sec. IV-A) cast angle votes; 0: every correspondence (Sec. IV-B) */
+    uint32_t angle_refine;   /* F: 0 or 1 = angle from the B-bin histogram; else in [2, 256] with
+                                B*F <= 65536: a second histogram over B*F bins, read on the 3F fine bins
+                                of coarse bins k-1, k, k+1 around the coarse peak k, gives the angle */
 } aoresp_params;
 
 /* Result of one rotation. */
@@ -81,6 +87,8 @@ typedef struct {
     uint32_t n_inliers;      /* number of i with ||R p_i - q_i|| <= tau */
     float R_ls[9];           /* least-squares rotation on that inlier set (float64 accumulation and solve,
                                 rounded); equals R when there are fewer than three inliers */
+    uint32_t angle_fine_bin;   /* bin of the B*F-bin histogram the angle comes from (0 without it) */
+    uint32_t angle_fine_votes; /* its votes (0 without it) */
 } aoresp_result;
 
 /* Grid resolution chosen for n when params.grid == 0: a pure function of n

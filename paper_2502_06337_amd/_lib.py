@@ -29,14 +29,16 @@ class AorespError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("grid", C.c_uint32), ("refine_grid", C.c_uint32), ("refine_halfwin", C.c_uint32),
-                ("angle_bins", C.c_uint32), ("nms_radius", C.c_uint32), ("inlier_thresh", C.c_float)]
+                ("angle_bins", C.c_uint32), ("nms_radius", C.c_uint32), ("inlier_thresh", C.c_float),
+                ("angle_gate", C.c_uint32), ("angle_refine", C.c_uint32)]
 
 
 class Result(C.Structure):
     _fields_ = [("R", C.c_float * 9), ("axis", C.c_float * 3), ("angle", C.c_float),
                 ("grid", C.c_uint32), ("peak_cell", C.c_uint32), ("fine_cell", C.c_uint32),
                 ("angle_bin", C.c_uint32), ("axis_votes", C.c_uint32), ("fine_votes", C.c_uint32),
-                ("angle_votes", C.c_uint32), ("n_inliers", C.c_uint32), ("R_ls", C.c_float * 9)]
+                ("angle_votes", C.c_uint32), ("n_inliers", C.c_uint32), ("R_ls", C.c_float * 9),
+                ("angle_fine_bin", C.c_uint32), ("angle_fine_votes", C.c_uint32)]
 
     def todict(self) -> dict:
         return {
@@ -48,6 +50,7 @@ class Result(C.Structure):
             "fine_votes": int(self.fine_votes), "angle_votes": int(self.angle_votes),
             "n_inliers": int(self.n_inliers),
             "R_ls": np.array(self.R_ls[:], dtype=np.float32).reshape(3, 3),
+            "angle_fine_bin": int(self.angle_fine_bin), "angle_fine_votes": int(self.angle_fine_votes),
         }
 
 
@@ -126,10 +129,12 @@ class SolveParams:
     angle_bins: int = 0
     nms_radius: int = 0
     inlier_thresh: float = 0.0
+    angle_gate: int = 0
+    angle_refine: int = 0
 
     def c(self) -> Params:
         return Params(self.grid, self.refine_grid, self.refine_halfwin, self.angle_bins, self.nms_radius,
-                      self.inlier_thresh)
+                      self.inlier_thresh, self.angle_gate, self.angle_refine)
 
 
 def _params(prm) -> Params:

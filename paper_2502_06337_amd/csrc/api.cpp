@@ -46,6 +46,8 @@ aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams&
     rp.B = p.angle_bins ? (int)p.angle_bins : 360;
     rp.rad = p.nms_radius ? (int)p.nms_radius : 5;
     rp.tau = p.inlier_thresh > 0.0f ? p.inlier_thresh : 0.05f;
+    rp.gate = (int)p.angle_gate;
+    rp.F = p.angle_refine > 1 ? (int)p.angle_refine : 1;
     if (!is_pow2((uint32_t)rp.G) || rp.G < 64 || rp.G > 4096) return AORESP_EINVAL;
     if (rp.M != 0 && (!is_pow2((uint32_t)rp.M) || rp.M < 8 || rp.M > 128 || (int64_t)rp.G * rp.M > 262144))
         return AORESP_EINVAL;
@@ -53,6 +55,8 @@ aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams&
     if (rp.B < 2 || rp.B > 8192) return AORESP_EINVAL;
     if (rp.rad > 1024) return AORESP_EINVAL;
     if (!std::isfinite(rp.tau)) return AORESP_EINVAL;
+    if (p.angle_gate > 1) return AORESP_EINVAL;
+    if (p.angle_refine > 256 || (int64_t)rp.B * rp.F > 65536) return AORESP_EINVAL;
     return AORESP_OK;
 }
 
@@ -248,6 +252,22 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         size_t lds = (size_t)rp.B * 8 + (size_t)I.npk * rp.B * 4;
         if (lds > 160 * 1024) return AORESP_EINVAL;
         if (lds > hist_lds) hist_lds = lds;
+        I.gate = rp.gate;
+        I.F = rp.F;
+        if (rp.F > 1) {
+            const AngleTables* ft = angle_tables(ctx, rp.B * rp.F);
+            if (!ft) return AORESP_ENOMEM;
+            I.ftc = ft->tc;
+            I.fts = ft->ts;
+            I.fth = ft->th;
+            I.fct = ft->ct;
+            I.fst = ft->st;
+            I.fhist_off = (int64_t)plan.fhist_cells;   // made absolute below
+            plan.fhist_cells += (size_t)I.npk * 3 * rp.F;
+            const size_t flds = angle_fine_lds_bytes(I.npk, rp.F);
+            if (flds > 160 * 1024) return AORESP_EINVAL;
+            if (flds > plan.fhist_lds) plan.fhist_lds = flds;
+        }
         // coarse-vote work split: forced (tuner candidate), tuned for (G, n), or default
         const Tuning tu = force ? *force : tuning_for(ctx, rp.G, n);
         const int bw = coarse_band_width(rp.G, tu.tile_cells);
@@ -284,6 +304,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
                 plan.list_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
             }
     }
+    for (Inst& I : plan.insts) I.fhist_off += (int64_t)plan.hist_cells;
     std::stable_sort(votes.begin(), votes.end(),
                      [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
     plan.vote_items.reserve(votes.size());
@@ -318,7 +339,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if ((st = w.geo.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
     if ((st = w.grid.ensure(plan.grid_cells * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.hist.ensure(plan.hist_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.hist.ensure((plan.hist_cells + plan.fhist_cells) * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
     const OutLayout ol(plan.nres);
     if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
@@ -372,7 +393,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     zero(keys, (size_t)plan.nres * 2);
     zero(w.grid.ptr, plan.grid_cells);
     zero(w.fine.ptr, plan.maxM > 0 ? plan.fine_cells : 0);
-    zero(w.hist.ptr, plan.hist_cells);
+    zero(w.hist.ptr, plan.hist_cells + plan.fhist_cells);
     zero(w.icount.ptr, (size_t)plan.nres * kCountSlots);
     launch_zero_list(zl, s);
     launch_arc_setup(P, Q, N, insts, ninst, R, s);
@@ -396,6 +417,12 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     launch_angle_hist(P, Q, N, insts, corr_items, (int)plan.corr_items.size(), stt, w.hist.as<uint32_t>(),
                       plan.hist_lds, s);
     for (int t = 0; t < plan.max_npk; ++t) launch_angle_peak(w.hist.as<uint32_t>(), insts, ninst, stt, t, res, s);
+    if (plan.fhist_lds > 0) {
+        launch_angle_fine_hist(P, Q, N, insts, corr_items, (int)plan.corr_items.size(), stt, res,
+                               w.hist.as<uint32_t>(), plan.fhist_lds, s);
+        for (int t = 0; t < plan.max_npk; ++t)
+            launch_angle_fine_peak(w.hist.as<uint32_t>(), insts, ninst, stt, t, res, s);
+    }
     mark(5);
     launch_inliers(P, Q, N, insts, ninst, stt, res, plan.nres, masks, w.icount.as<uint32_t>(), s);
     for (int t = 0; t < plan.max_npk; ++t) {
@@ -504,7 +531,7 @@ aoresp_status reserve_plan(Workspace& w, const Plan& plan) {
     if ((st = w.geo.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
     if ((st = w.grid.ensure(plan.grid_cells * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.hist.ensure(plan.hist_cells * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.hist.ensure((plan.hist_cells + plan.fhist_cells) * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
     const OutLayout ol(plan.nres);
     if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;

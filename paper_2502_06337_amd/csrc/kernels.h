@@ -64,6 +64,14 @@ struct Inst {
     const float* th;
     const float* ct;
     const float* st;
+    int32_t gate;         // angle gate: only correspondences voting for a cell of the peak's window vote
+    int32_t F;            // fine angle factor (1 = none): B*F-bin tables below, 3F window counters per peak
+    int64_t fhist_off;    // u32 offset of its npk fine-angle windows (3F each) in the histogram arena
+    const float* ftc;     // angle tables for B*F
+    const float* fts;
+    const float* fth;
+    const float* fct;
+    const float* fst;
 };
 
 struct FineWin {
@@ -123,6 +131,16 @@ void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* in
                        const PeakState* st, uint32_t* hist_arena, size_t lds_bytes, hipStream_t s);
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                        aoresp_result* res, hipStream_t s);
+// Coarse-to-fine angle voting: the B*F-bin histogram of every valid peak,
+// counted only on the 3F fine bins of coarse bins k-1, k, k+1 around the
+// coarse angle peak k (cyclic, in that order), then its argmax (ties to the
+// first) replaces the angle and R.  Instances with F = 1 are skipped.
+size_t angle_fine_lds_bytes(int npk, int F);
+void launch_angle_fine_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items,
+                            int nitems, const PeakState* st, const aoresp_result* res, uint32_t* hist_arena,
+                            size_t lds_bytes, hipStream_t s);
+void launch_angle_fine_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, const PeakState* st, int slot,
+                            aoresp_result* res, hipStream_t s);
 // Least-squares rotation on the inlier set of result slot `slot`: per
 // correspondence item, the float64 sums of p q^T over the inliers and their
 // count (kLsWords doubles per item, in partial); then per instance the sums of

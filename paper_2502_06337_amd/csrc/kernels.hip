@@ -12,8 +12,12 @@
 //   k_fine_vote      refinement accumulator around each peak
 //   k_fine_peak      refined cell, inverse projection to the axis (Eq. (8))
 //   k_angle_hist     signed angle of every pair about the axis, binned
-//                    (Sec. IV-B, Eq. (10))
+//                    (Sec. IV-B, Eq. (10)); optionally only the pairs whose
+//                    curve crosses the peak's window of coarse cells
 //   k_angle_peak     histogram peak, Rodrigues rotation (Eq. (2))
+//   k_angle_fine_hist / k_angle_fine_peak
+//                    optional B*F-bin histogram read on the three coarse bins
+//                    around the angle peak; its argmax replaces the angle
 //   k_inliers        residual mask against Eq. (1)
 //   k_ls_accum       float64 sums of p q^T over the inliers, per item
 //   k_ls_finish      least-squares rotation on the inlier set (quaternion
@@ -834,8 +838,58 @@ __device__ __forceinline__ int angle_bin(const float* tc, const float* ts, int B
     return lo;
 }
 
+// Angle gate (coarse-to-fine angle voting): does the correspondence with
+// displacement d = p - q vote for a coarse cell of [x0, x1] x [y0, y1] by the
+// per-cell rule of Sec. IV-A (a corner in the closed disk, corners with
+// F <= 0 and with F >= 0)?  Vertex values are formed in the same order as the
+// accumulator's: W = ((u u) + (v v)) - 1, F = (c W) + 2 ((a u) + (b v)).  Each
+// row of cells is swept left to right, reusing the shared edge.
+__device__ __forceinline__ void gate_vertex(float a, float b, float c, float u, float v, float& W, float& F) {
+    float uu = u * u;
+    float vv = v * v;
+    W = (uu + vv) - 1.0f;
+    float cw = c * W;
+    float au = a * u;
+    float bv = b * v;
+    float t = au + bv;
+    float t2 = 2.0f * t;
+    F = cw + t2;
+}
+
+__device__ bool window_hit(const float* p, const float* q, int G, uint32_t cell, int w) {
+    const float a = p[0] - q[0], b = p[1] - q[1], c = p[2] - q[2];
+    if (!(isfinite(a) && isfinite(b) && isfinite(c))) return false;
+    if (a == 0.0f && b == 0.0f && c == 0.0f) return false;
+    const int px = (int)(cell % (uint32_t)G), py = (int)(cell / (uint32_t)G);
+    const int x0 = px - w < 0 ? 0 : px - w, x1 = px + w > G - 1 ? G - 1 : px + w;
+    const int y0 = py - w < 0 ? 0 : py - w, y1 = py + w > G - 1 ? G - 1 : py + w;
+    const float h = 2.0f / (float)G;
+    for (int iy = y0; iy <= y1; ++iy) {
+        const float v0 = -1.0f + (float)iy * h, v1 = -1.0f + (float)(iy + 1) * h;
+        const float ul = -1.0f + (float)x0 * h;
+        float w0, f0, w1, f1;
+        gate_vertex(a, b, c, ul, v0, w0, f0);
+        gate_vertex(a, b, c, ul, v1, w1, f1);
+        for (int ix = x0; ix <= x1; ++ix) {
+            const float ur = -1.0f + (float)(ix + 1) * h;
+            float w2, f2, w3, f3;
+            gate_vertex(a, b, c, ur, v0, w2, f2);
+            gate_vertex(a, b, c, ur, v1, w3, f3);
+            const bool disk = (w0 <= 0.0f) | (w1 <= 0.0f) | (w2 <= 0.0f) | (w3 <= 0.0f);
+            const bool le = (f0 <= 0.0f) | (f1 <= 0.0f) | (f2 <= 0.0f) | (f3 <= 0.0f);
+            const bool ge = (f0 >= 0.0f) | (f1 >= 0.0f) | (f2 >= 0.0f) | (f3 >= 0.0f);
+            if (disk && le && ge) return true;
+            w0 = w2;
+            f0 = f2;
+            w1 = w3;
+            f1 = f3;
+        }
+    }
+    return false;
+}
+
 // Histograms of every valid peak of the item's instance over correspondences
-// [i0, i1) of that instance.
+// [i0, i1) of that instance (those that pass the peak's gate when it is on).
 __global__ __launch_bounds__(512) void k_angle_hist(const float* __restrict__ P, const float* __restrict__ Q,
                                                     int64_t N, const Inst* __restrict__ insts,
                                                     const int4* __restrict__ items, const PeakState* st,
@@ -843,7 +897,8 @@ __global__ __launch_bounds__(512) void k_angle_hist(const float* __restrict__ P,
     extern __shared__ __align__(16) uint32_t sm[];
     const int4 wi = items[blockIdx.x];
     const Inst& I = insts[wi.x];
-    const int B = I.B, npk = I.npk;
+    const int B = I.B, npk = I.npk, G = I.G, w = I.w;
+    const bool gate = I.gate != 0;
     float* tc = reinterpret_cast<float*>(sm);
     float* ts = tc + B;
     uint32_t* hl = reinterpret_cast<uint32_t*>(ts + B);
@@ -854,11 +909,13 @@ __global__ __launch_bounds__(512) void k_angle_hist(const float* __restrict__ P,
     for (int t = threadIdx.x; t < npk * B; t += blockDim.x) hl[t] = 0u;
     float ax[kMaxPeaks][3];
     bool valid[kMaxPeaks];
+    uint32_t pc[kMaxPeaks];
     for (int t = 0; t < kMaxPeaks; ++t) {
         valid[t] = t < npk && st[I.res_off + t].valid;
         ax[t][0] = valid[t] ? st[I.res_off + t].axis[0] : 0.0f;
         ax[t][1] = valid[t] ? st[I.res_off + t].axis[1] : 0.0f;
         ax[t][2] = valid[t] ? st[I.res_off + t].axis[2] : 0.0f;
+        pc[t] = valid[t] ? st[I.res_off + t].peak_cell : 0u;
     }
     __syncthreads();
     for (int64_t li = wi.y + threadIdx.x; li < wi.z; li += blockDim.x) {
@@ -867,6 +924,7 @@ __global__ __launch_bounds__(512) void k_angle_hist(const float* __restrict__ P,
         float q[3] = {Q[i], Q[N + i], Q[2 * N + i]};
         for (int t = 0; t < npk; ++t) {
             if (!valid[t]) continue;
+            if (gate && !window_hit(p, q, G, pc[t], w)) continue;
             float X, Y;
             angle_xy(ax[t], p, q, X, Y);
             int bin = angle_bin(tc, ts, B, X, Y);
@@ -881,8 +939,29 @@ __global__ __launch_bounds__(512) void k_angle_hist(const float* __restrict__ P,
     }
 }
 
-// Histogram peak (ties to the lowest bin), then R = I + sin K + (1 - cos) K^2
-// with K = [r]x (Eq. (2)).  One block per instance.
+// R = I + sin K + (1 - cos) K^2 with K = [r]x (Eq. (2)), row-major.
+__device__ void rodrigues(const float* r, float ct, float sn, float* R) {
+    float K[9] = {0.0f, -r[2], r[1], r[2], 0.0f, -r[0], -r[1], r[0], 0.0f};
+    float K2[9];
+    for (int j = 0; j < 3; ++j)
+        for (int l = 0; l < 3; ++l) {
+            float t0 = K[j * 3 + 0] * K[0 * 3 + l];
+            float t1 = K[j * 3 + 1] * K[1 * 3 + l];
+            float t2 = K[j * 3 + 2] * K[2 * 3 + l];
+            K2[j * 3 + l] = (t0 + t1) + t2;
+        }
+    float om = 1.0f - ct;
+    for (int j = 0; j < 3; ++j)
+        for (int l = 0; l < 3; ++l) {
+            float delta = (j == l) ? 1.0f : 0.0f;
+            float a = sn * K[j * 3 + l];
+            float bb = om * K2[j * 3 + l];
+            R[j * 3 + l] = (delta + a) + bb;
+        }
+}
+
+// Histogram peak (ties to the lowest bin), then R from the bin centre.  One
+// block per instance.
 __global__ __launch_bounds__(1024) void k_angle_peak(const uint32_t* __restrict__ hist_arena,
                                                      const Inst* __restrict__ insts, PeakState* st, int slot,
                                                      aoresp_result* res) {
@@ -913,28 +992,10 @@ __global__ __launch_bounds__(1024) void k_angle_peak(const uint32_t* __restrict_
         return;
     }
     uint32_t bin = ~(uint32_t)(best & 0xFFFFFFFFull);
-    float ct = I.ct[bin], sn = I.st[bin];
-    const float* r = s.axis;
-    float K[9] = {0.0f, -r[2], r[1], r[2], 0.0f, -r[0], -r[1], r[0], 0.0f};
-    float K2[9];
-    for (int j = 0; j < 3; ++j)
-        for (int l = 0; l < 3; ++l) {
-            float t0 = K[j * 3 + 0] * K[0 * 3 + l];
-            float t1 = K[j * 3 + 1] * K[1 * 3 + l];
-            float t2 = K[j * 3 + 2] * K[2 * 3 + l];
-            K2[j * 3 + l] = (t0 + t1) + t2;
-        }
-    float om = 1.0f - ct;
-    for (int j = 0; j < 3; ++j)
-        for (int l = 0; l < 3; ++l) {
-            float delta = (j == l) ? 1.0f : 0.0f;
-            float a = sn * K[j * 3 + l];
-            float bb = om * K2[j * 3 + l];
-            o.R[j * 3 + l] = (delta + a) + bb;
-        }
-    o.axis[0] = r[0];
-    o.axis[1] = r[1];
-    o.axis[2] = r[2];
+    rodrigues(s.axis, I.ct[bin], I.st[bin], o.R);
+    o.axis[0] = s.axis[0];
+    o.axis[1] = s.axis[1];
+    o.axis[2] = s.axis[2];
     o.angle = I.th[bin];
     o.peak_cell = s.peak_cell;
     o.fine_cell = s.fine_cell;
@@ -942,6 +1003,122 @@ __global__ __launch_bounds__(1024) void k_angle_peak(const uint32_t* __restrict_
     o.axis_votes = s.axis_votes;
     o.fine_votes = s.fine_votes;
     o.angle_votes = (uint32_t)(best >> 32);
+}
+
+// Coarse bin of window slot j (0, 1, 2 = k-1, k, k+1, cyclic) around bin k.
+__device__ __forceinline__ int fine_slot_bin(int k, int j, int B) { return (k + j + B - 1) % B; }
+
+// LDS of the fine pass: per peak and window slot, the F+1 boundary directions
+// cF .. cF+F of the B*F table (cos and sin), then 3F counters per peak.
+size_t angle_fine_lds_bytes(int npk, int F) {
+    return (size_t)npk * 3 * (size_t)(F + 1) * 8 + (size_t)npk * 3 * (size_t)F * 4;
+}
+
+// Fine angle votes.  With the boundary predicate monotone in the boundary
+// index, a direction lies in coarse slot c's fine bins [cF, (c+1)F) iff
+// boundary cF is at or below it (always, for c = 0) and boundary (c+1)F is
+// not (always, for c = B-1); its fine bin is then cF plus the number of the
+// slot's interior boundaries at or below it, found by binary search.  A slot
+// that repeats a coarse bin (B < 3) counts the same votes again, as a window
+// read of the full B*F histogram would.
+__global__ __launch_bounds__(512) void k_angle_fine_hist(const float* __restrict__ P, const float* __restrict__ Q,
+                                                         int64_t N, const Inst* __restrict__ insts,
+                                                         const int4* __restrict__ items, const PeakState* st,
+                                                         const aoresp_result* res,
+                                                         uint32_t* __restrict__ hist_arena) {
+    extern __shared__ __align__(16) uint32_t sm[];
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
+    const int F = I.F;
+    if (F <= 1) return;
+    const int B = I.B, npk = I.npk, G = I.G, w = I.w, BF = B * F, nb = F + 1;
+    const bool gate = I.gate != 0;
+    float* bc = reinterpret_cast<float*>(sm);
+    float* bs = bc + (size_t)npk * 3 * nb;
+    uint32_t* hl = reinterpret_cast<uint32_t*>(bs + (size_t)npk * 3 * nb);
+    float ax[kMaxPeaks][3];
+    bool valid[kMaxPeaks];
+    uint32_t pc[kMaxPeaks];
+    int kb[kMaxPeaks];
+    for (int t = 0; t < kMaxPeaks; ++t) {
+        valid[t] = t < npk && st[I.res_off + t].valid;
+        ax[t][0] = valid[t] ? st[I.res_off + t].axis[0] : 0.0f;
+        ax[t][1] = valid[t] ? st[I.res_off + t].axis[1] : 0.0f;
+        ax[t][2] = valid[t] ? st[I.res_off + t].axis[2] : 0.0f;
+        pc[t] = valid[t] ? st[I.res_off + t].peak_cell : 0u;
+        kb[t] = valid[t] ? (int)res[I.res_off + t].angle_bin : 0;
+    }
+    for (int e = threadIdx.x; e < npk * 3 * nb; e += blockDim.x) {
+        const int t = e / (3 * nb), j = (e / nb) % 3, m = e % nb;
+        const int kt = t < npk ? (int)res[I.res_off + t].angle_bin : 0;
+        const int g = fine_slot_bin(kt % B, j, B) * F + m;
+        bc[e] = g < BF ? I.ftc[g] : 0.0f;
+        bs[e] = g < BF ? I.fts[g] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < npk * 3 * F; e += blockDim.x) hl[e] = 0u;
+    __syncthreads();
+    for (int64_t li = wi.y + threadIdx.x; li < wi.z; li += blockDim.x) {
+        const int64_t i = I.off + li;
+        float p[3] = {P[i], P[N + i], P[2 * N + i]};
+        float q[3] = {Q[i], Q[N + i], Q[2 * N + i]};
+        for (int t = 0; t < npk; ++t) {
+            if (!valid[t]) continue;
+            if (gate && !window_hit(p, q, G, pc[t], w)) continue;
+            float X, Y;
+            angle_xy(ax[t], p, q, X, Y);
+            if (!(isfinite(X) && isfinite(Y))) continue;
+            if (X == 0.0f && Y == 0.0f) continue;
+            const int hv = half_plane(X, Y);
+            for (int j = 0; j < 3; ++j) {
+                const int c = fine_slot_bin(kb[t], j, B);
+                const float* tc = bc + (size_t)(t * 3 + j) * nb;
+                const float* ts = bs + (size_t)(t * 3 + j) * nb;
+                if (c != 0 && !at_or_below(tc[0], ts[0], hv, X, Y)) continue;
+                if (c != B - 1 && at_or_below(tc[F], ts[F], hv, X, Y)) continue;
+                int lo = 0, hi = F - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (at_or_below(tc[mid], ts[mid], hv, X, Y)) lo = mid; else hi = mid - 1;
+                }
+                atomicAdd(&hl[(t * 3 + j) * F + lo], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t* hist = hist_arena + I.fhist_off;
+    for (int e = threadIdx.x; e < npk * 3 * F; e += blockDim.x) {
+        const uint32_t v = hl[e];
+        if (v) atomicAdd(&hist[e], v);
+    }
+}
+
+// Argmax of the 3F window counters (ties to the first in window order); the
+// fine bin's centre replaces the angle and R.  One block per instance.
+__global__ __launch_bounds__(256) void k_angle_fine_peak(const uint32_t* __restrict__ hist_arena,
+                                                         const Inst* __restrict__ insts, const PeakState* st, int slot,
+                                                         aoresp_result* res) {
+    __shared__ unsigned long long red[4];
+    const Inst& I = insts[blockIdx.x];
+    if (slot >= I.npk || I.F <= 1) return;
+    const PeakState& s = st[I.res_off + slot];
+    if (!s.valid) return;
+    aoresp_result& o = res[I.res_off + slot];
+    const int F = I.F, B = I.B, W3 = 3 * F;
+    const uint32_t* h = hist_arena + I.fhist_off + (size_t)slot * W3;
+    unsigned long long best = 0ull;
+    for (int e = threadIdx.x; e < W3; e += blockDim.x) {
+        unsigned long long k = ((unsigned long long)h[e] << 32) | (unsigned long long)(~(uint32_t)e);
+        best = k > best ? k : best;
+    }
+    best = block_max_u64(best, red);
+    if (threadIdx.x != 0) return;
+    // keys carry ~index, so an all-zero window yields its first entry
+    const int e = (int)~(uint32_t)(best & 0xFFFFFFFFull);
+    const int jf = fine_slot_bin((int)o.angle_bin, e / F, B) * F + e % F;
+    rodrigues(s.axis, I.fct[jf], I.fst[jf], o.R);
+    o.angle = I.fth[jf];
+    o.angle_fine_bin = (uint32_t)jf;
+    o.angle_fine_votes = (uint32_t)(best >> 32);
 }
 
 // ||R p - q||^2 <= tau^2 per correspondence (Eq. (1)); masks[slot*N + i] if
@@ -1141,6 +1318,7 @@ void init_kernel_attributes() {
     set_lds_limit((const void*)k_vote);
     set_lds_limit((const void*)k_fine_vote);
     set_lds_limit((const void*)k_angle_hist);
+    set_lds_limit((const void*)k_angle_fine_hist);
 }
 
 void launch_zero_list(const ZeroList& zl, hipStream_t s) {
@@ -1208,6 +1386,20 @@ void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* in
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                        aoresp_result* res, hipStream_t s) {
     hipLaunchKernelGGL(k_angle_peak, dim3((unsigned)ninst), dim3(1024), 0, s, hist_arena, insts, st, slot, res);
+}
+
+void launch_angle_fine_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items,
+                            int nitems, const PeakState* st, const aoresp_result* res, uint32_t* hist_arena,
+                            size_t lds_bytes, hipStream_t s) {
+    if (nitems <= 0 || lds_bytes == 0) return;
+    hipLaunchKernelGGL(k_angle_fine_hist, dim3((unsigned)nitems), dim3(512), lds_bytes, s, P, Q, N, insts, items, st,
+                       res, hist_arena);
+}
+
+void launch_angle_fine_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, const PeakState* st, int slot,
+                            aoresp_result* res, hipStream_t s) {
+    if (ninst <= 0) return;
+    hipLaunchKernelGGL(k_angle_fine_peak, dim3((unsigned)ninst), dim3(256), 0, s, hist_arena, insts, st, slot, res);
 }
 
 void launch_ls_accum(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,

@@ -15,6 +15,7 @@ namespace aoresp {
 struct ResolvedParams {
     int G, M, w, B, rad;
     float tau;
+    int gate, F;   // angle gate on/off; fine angle factor (1 = none)
 };
 
 aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams& rp);
@@ -83,9 +84,11 @@ struct Plan {
     std::vector<int4> vote_items, cell_items, corr_items, list_items;
     int64_t N = 0;
     size_t grid_cells = 0, fine_cells = 0, hist_cells = 0;
+    size_t fhist_cells = 0;    // fine-angle windows, after the histograms in the same arena
     int nres = 0;              // result slots (sum of npk)
     int max_npk = 0, maxM = 0;
     size_t hist_lds = 0;
+    size_t fhist_lds = 0;      // 0: no instance refines its angle
 };
 
 // Work split of the coarse vote for one (G, n bucket): LDS tile cells and

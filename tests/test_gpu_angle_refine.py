@@ -1,0 +1,170 @@
+"""GPU parity of coarse-to-fine angle voting (gate on the peak's window of
+coarse cells, then a B*F-bin histogram read on the three coarse bins around
+the angle peak) against the oracle, through the C ABI.
+
+The expected result is composed from oracle functions only: the oracle's
+solve gives the axis stage (peak, refinement, axis), the oracle's
+coarse-to-fine angle vote gives the angle bins, angle and R, the oracle's
+inlier test gives the mask and count, and its float64 Kabsch solve the
+least-squares rotation.  Bins, votes, masks, angle and R are compared bit for
+bit; the least-squares rotation within 2^-22 per entry.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2502_06337_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LS_TOL = 2.0 ** -22
+
+
+@pytest.fixture(scope="module")
+def aor():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_06337_amd as aor
+    aor.load_library()
+    return aor
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def expected(orc, P, Q, base, G, w, B, F, gate, tau=0.05):
+    """The oracle's answer for one peak whose axis stage is `base` (a result
+    of the oracle's solve or top-k solve)."""
+    c2f = orc.angle_coarse_to_fine(P, Q, base["axis"], G, base["peak_cell"], w, B, F, gate=bool(gate))
+    mask, cnt = orc.inliers(c2f["R"], P, Q, tau)
+    out = dict(base)
+    out.update({"angle_bin": c2f["angle_bin"], "angle_votes": c2f["angle_votes"],
+                "angle_fine_bin": c2f["angle_fine_bin"], "angle_fine_votes": c2f["angle_fine_votes"],
+                "angle": np.float32(c2f["angle"]), "R": np.asarray(c2f["R"], np.float32),
+                "n_inliers": cnt, "mask": mask})
+    return out, c2f
+
+
+def assert_same(orc, r, e, P, Q, mask=None):
+    for key in ("peak_cell", "axis_votes", "fine_cell", "fine_votes", "angle_bin", "angle_votes",
+                "angle_fine_bin", "angle_fine_votes", "n_inliers"):
+        assert r[key] == e[key], (key, r[key], e[key])
+    assert np.array_equal(r["axis"].view(np.uint32), e["axis"].view(np.uint32))
+    assert np.float32(r["angle"]).view(np.uint32) == np.float32(e["angle"]).view(np.uint32), (r["angle"], e["angle"])
+    assert np.array_equal(r["R"].view(np.uint32), e["R"].view(np.uint32)), (r["R"], e["R"])
+    if mask is not None:
+        assert np.array_equal(mask, e["mask"])
+    ref = orc.ls_rotation(P, Q, e["mask"])
+    if ref is None:
+        assert np.array_equal(r["R_ls"].view(np.uint32), r["R"].view(np.uint32))
+    else:
+        assert np.max(np.abs(r["R_ls"].astype(np.float64) - ref)) <= LS_TOL
+
+
+CASES = [
+    # (G, M, w, B, F, gate, n, seed)
+    (256, 0, 1, 360, 10, 1, 3000, 11),     # paper-like bins, gate and ten fine bins per degree
+    (128, 32, 1, 720, 4, 1, 2000, 12),     # with a refinement grid
+    (256, 0, 1, 360, 1, 1, 2000, 13),      # gate only
+    (256, 0, 1, 360, 16, 0, 2000, 14),     # fine bins only
+    (64, 0, 2, 2, 8, 1, 600, 15),          # B = 2: the window repeats a coarse bin
+    (64, 0, 1, 3, 5, 0, 600, 16),          # B = 3: the window is the whole circle
+    (128, 0, 1, 256, 256, 1, 1500, 17),    # F and B*F at their maxima
+    (64, 0, 8, 360, 10, 1, 1500, 18),      # widest gate window
+]
+
+
+@pytest.mark.parametrize("G,M,w,B,F,gate,n,seed", CASES)
+def test_gate_and_fine_angle_match_oracle(aor, orc, G, M, w, B, F, gate, n, seed):
+    inst = synth.make_instance(n, 4100 + seed, outlier_rate=0.9, sigma=0.01)
+    prm = aor.SolveParams(grid=G, refine_grid=M, refine_halfwin=w, angle_bins=B, angle_gate=gate, angle_refine=F)
+    r, m, st = aor.est_rotation(dev(inst.P), dev(inst.Q), prm)
+    assert st == 0
+    base = orc.solve(inst.P, inst.Q, G=G, B=B, M=M, w=w)
+    e, c2f = expected(orc, inst.P, inst.Q, base, G, w, B, F, gate)
+    assert_same(orc, r, e, inst.P, inst.Q, m.cpu().numpy())
+    if gate:
+        assert c2f["gate"].sum() < n   # the gate drops correspondences
+    if F <= 1:
+        assert r["angle_fine_bin"] == 0 and r["angle_fine_votes"] == 0
+
+
+def test_defaults_unchanged(aor, orc):
+    """Gate off and F = 0 reproduce the plain solve of Sec. IV-B."""
+    inst = synth.make_instance(1500, 4200)
+    prm = aor.SolveParams(grid=128, angle_bins=360, angle_gate=0, angle_refine=0)
+    r, _, _ = aor.est_rotation(inst.P, inst.Q, prm)
+    base = orc.solve(inst.P, inst.Q, G=128, B=360)
+    for key in ("angle_bin", "angle_votes", "n_inliers"):
+        assert r[key] == base[key]
+    assert np.array_equal(r["R"].view(np.uint32), base["R"].view(np.uint32))
+    assert r["angle_fine_bin"] == 0 and r["angle_fine_votes"] == 0
+
+
+def rot(axis, t):
+    axis = np.asarray(axis, dtype=np.float64) / np.linalg.norm(axis)
+    K = np.array([[0, -axis[2], axis[1]], [axis[2], 0, -axis[0]], [-axis[1], axis[0], 0]])
+    return np.eye(3) + math.sin(t) * K + (1 - math.cos(t)) * K @ K
+
+
+@pytest.mark.parametrize("uv,t", [((0.995, 0.01), 0.7), ((-0.02, -0.997), -3.1), ((0.3, -0.2), 3.14)])
+def test_gate_window_clipped_and_angle_wraps(aor, orc, uv, t):
+    """Axis next to the grid's border (the gate window is clipped) and angles
+    next to +-pi (the fine window wraps round the circle)."""
+    u, v = uv
+    s = u * u + v * v
+    r = np.array([2 * u / (1 + s), 2 * v / (1 + s), (s - 1) / (1 + s)])
+    rng = np.random.default_rng(int(1000 * (u + 2)) + 7)
+    n = 1200
+    P = rng.uniform(-1, 1, (3, n)).astype(np.float32)
+    Q = rng.uniform(-1, 1, (3, n)).astype(np.float32)
+    Q[:, :300] = (rot(r, t) @ P[:, :300].astype(np.float64)).astype(np.float32)
+    G, M, B, F = 128, 32, 360, 12
+    prm = aor.SolveParams(grid=G, refine_grid=M, angle_bins=B, angle_gate=1, angle_refine=F)
+    res, m, st = aor.est_rotation(dev(P), dev(Q), prm)
+    assert st == 0
+    base = orc.solve(P, Q, G=G, B=B, M=M)
+    e, _ = expected(orc, P, Q, base, G, 1, B, F, 1)
+    assert_same(orc, res, e, P, Q, m.cpu().numpy())
+
+
+def test_topk_gate_and_fine_angle(aor, orc):
+    """Three rotations, 10% inliers each: every peak gates on its own window
+    and refines its own angle."""
+    inst = synth.make_instance(3000, 4300, n_rot=3, inlier_frac_each=0.1, sigma=0.01)
+    G, B, k, M, F = 128, 360, 3, 16, 10
+    prm = aor.SolveParams(grid=G, angle_bins=B, nms_radius=5, refine_grid=M, angle_gate=1, angle_refine=F)
+    outs, masks, st = aor.est_rotations_topk(dev(inst.P), dev(inst.Q), k, prm)
+    masks = masks.cpu().numpy()
+    ors = orc.solve_topk(inst.P, inst.Q, G=G, B=B, k=k, rad=5, M=M)
+    assert len(outs) == len(ors) == 3
+    for t, (a, b) in enumerate(zip(outs, ors)):
+        e, _ = expected(orc, inst.P, inst.Q, b, G, 1, B, F, 1)
+        assert_same(orc, a, e, inst.P, inst.Q, masks[t])
+
+
+def test_batch_mixed_angle_options(aor):
+    """A batch whose instances differ in gate and F: each result equals its
+    one-at-a-time solve."""
+    sizes = [1500, 700, 0, 2500, 900]
+    insts = [synth.make_instance(max(n, 1), 4400 + t) for t, n in enumerate(sizes)]
+    P = np.concatenate([i.P[:, :n] for i, n in zip(insts, sizes)], axis=1)
+    Q = np.concatenate([i.Q[:, :n] for i, n in zip(insts, sizes)], axis=1)
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    opts = [(1, 10), (0, 1), (1, 4), (0, 20), (1, 0)]
+    prms = [aor.SolveParams(grid=128, angle_bins=360, angle_gate=g, angle_refine=f) for g, f in opts]
+    outs, mask, st = aor.est_rotation_batch(dev(P), dev(Q), off, prms)
+    mask = mask.cpu().numpy()
+    for t, n in enumerate(sizes):
+        if n < 2:
+            continue
+        r1, m1, _ = aor.est_rotation(insts[t].P[:, :n], insts[t].Q[:, :n], prms[t])
+        for key in ("angle_bin", "angle_votes", "angle_fine_bin", "angle_fine_votes", "n_inliers", "peak_cell"):
+            assert outs[t][key] == r1[key], (t, key)
+        assert np.array_equal(outs[t]["R"].view(np.uint32), r1["R"].view(np.uint32))
+        assert np.array_equal(outs[t]["R_ls"].view(np.uint32), r1["R_ls"].view(np.uint32))
+        assert np.array_equal(mask[off[t]:off[t + 1]], m1)

@@ -307,6 +307,22 @@ def test_paper_scale_sampled_parity(aor, orc):
     assert_ls(orc, r, inst.P, inst.Q, fin["mask"])
     # the least-squares rotation on 1e5 inliers with sigma = 0.01 lands far below a cell
     assert orc.rotation_error_deg(inst.R_gt[0], r["R_ls"]) < 0.01
+    # the same launch with coarse-to-fine angle voting (gate on the 3 x 3
+    # window, 36000 fine bins): the axis stage is unchanged, the angle stage
+    # against the oracle's coarse-to-fine vote on the oracle's axis
+    prm = aor.SolveParams(grid=G, refine_grid=M, angle_bins=B, angle_gate=1, angle_refine=10)
+    r2, m2, st = aor.est_rotation(dev(inst.P), dev(inst.Q), prm)
+    c2f = orc.angle_coarse_to_fine(inst.P, inst.Q, fin["axis"], G, fin["peak_cell"], 1, B, 10)
+    mask2, cnt2 = orc.inliers(c2f["R"], inst.P, inst.Q, 0.05)
+    for key in ("peak_cell", "fine_cell", "axis_votes", "fine_votes"):
+        assert r2[key] == r[key]
+    for key in ("angle_bin", "angle_votes", "angle_fine_bin", "angle_fine_votes"):
+        assert r2[key] == c2f[key], (key, r2[key], c2f[key])
+    assert np.float32(r2["angle"]).view(np.uint32) == np.float32(c2f["angle"]).view(np.uint32)
+    assert np.array_equal(r2["R"].view(np.uint32), np.asarray(c2f["R"], np.float32).view(np.uint32))
+    assert r2["n_inliers"] == cnt2
+    assert np.array_equal(m2.cpu().numpy(), mask2)
+    assert_ls(orc, r2, inst.P, inst.Q, mask2)
 
 
 def rot(axis, t):
