@@ -89,6 +89,11 @@ def lib():
             "or_arc_votes": (C.c_long, [_fp, _fp, C.c_int]),
             "or_argmax": (C.c_uint32, [_u32p, C.c_long, _lp]),
             "or_window_gate": (None, [_fp, _fp, C.c_long, C.c_int, C.c_int, C.c_int, C.c_int, _u8p]),
+            "or_sample_dirs": (None, [C.c_int, _fp, _fp]),
+            "or_sample_basis": (C.c_int, [_fp, _fp, _fp, _fp, _fp]),
+            "or_sample_point": (None, [_fp, _fp, _f, _f, _fp]),
+            "or_sample_cell": (C.c_long, [_fp, C.c_int]),
+            "or_sample_grid": (None, [_fp, _fp, C.c_long, C.c_int, C.c_int, _u32p]),
             "or_fine_window": (None, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(Window)]),
             "or_fine_grid": (None, [_fp, _fp, C.c_long, C.POINTER(Window), _u32p]),
             "or_fine_cell": (C.c_uint32, [_fp, _fp, C.c_long, C.POINTER(Window), C.c_int, C.c_int]),
@@ -163,6 +168,49 @@ def coarse_cell(P, Q, G: int, ix: int, iy: int) -> int:
 def arc_votes(p, q, G: int) -> int:
     p, q = _f32(p), _f32(q)
     return int(lib().or_arc_votes(_ptr(p, _fp), _ptr(q, _fp), G))
+
+
+# ------------------------------------------------- literal sampling rule
+def sample_dirs(J: int) -> tuple[np.ndarray, np.ndarray]:
+    cs, sn = np.zeros(J, np.float32), np.zeros(J, np.float32)
+    lib().or_sample_dirs(J, _ptr(cs, _fp), _ptr(sn, _fp))
+    return cs, sn
+
+
+def sample_basis(p, q):
+    """(z, alpha1, alpha2) of Algorithm 1 for one correspondence, or None."""
+    p, q = _f32(p), _f32(q)
+    z, a1, a2 = (np.zeros(3, np.float32) for _ in range(3))
+    ok = lib().or_sample_basis(_ptr(p, _fp), _ptr(q, _fp), _ptr(z, _fp), _ptr(a1, _fp), _ptr(a2, _fp))
+    return (z, a1, a2) if ok else None
+
+
+def sample_points(p, q, J: int) -> np.ndarray:
+    """The J sample points of one correspondence's great circle, (3, J)."""
+    b = sample_basis(p, q)
+    if b is None:
+        return np.zeros((3, 0), np.float32)
+    _, a1, a2 = b
+    cs, sn = sample_dirs(J)
+    out = np.zeros((3, J), np.float32)
+    s = np.zeros(3, np.float32)
+    for j in range(J):
+        lib().or_sample_point(_ptr(a1, _fp), _ptr(a2, _fp), cs[j], sn[j], _ptr(s, _fp))
+        out[:, j] = s
+    return out
+
+
+def sample_cell(s, G: int) -> int:
+    s = _f32(s)
+    return int(lib().or_sample_cell(_ptr(s, _fp), G))
+
+
+def sample_grid(P, Q, G: int, J: int) -> np.ndarray:
+    """Coarse accumulator by the literal sampling rule (J samples per circle)."""
+    P, Q = _f32(P), _f32(Q)
+    g = np.zeros(G * G, dtype=np.uint32)
+    lib().or_sample_grid(_ptr(P, _fp), _ptr(Q, _fp), P.shape[1], G, J, _ptr(g, _u32p))
+    return g.reshape(G, G)
 
 
 def argmax(a) -> tuple[int, int]:

@@ -43,6 +43,11 @@
  *     table of bin-boundary directions.
  *   - a correspondence whose displacement is zero or non-finite casts no axis
  *     vote; one whose (X, Y) is (0, 0) or non-finite casts no angle vote.
+ *   - the literal sampling rule of Algorithm 1 (kept as a selectable
+ *     alternative): the garbled sample expression is read as
+ *     alpha1 cos(theta_j) + alpha2 sin(theta_j), alpha0 as the coordinate axis
+ *     of z's smallest component, theta_j = -pi + j 2pi/J; only samples on the
+ *     closed southern hemisphere vote, one vote per sample.
  */
 #include <math.h>
 #include <stdint.h>
@@ -199,6 +204,111 @@ OR_EXPORT long or_arc_votes(const float* p, const float* q, int G) {
     for (int iy = 0; iy < G; ++iy)
         for (int ix = 0; ix < G; ++ix) cnt += or_coarse_hit(p, q, G, ix, iy);
     return cnt;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Literal sampling rule (Algorithm 1's inner loop; a selectable alternative */
+/* to the per-cell rule above)                                              */
+/* ------------------------------------------------------------------------ */
+
+/* Sample directions theta_j = -pi + j*(2pi/J), j = 0..J-1 (Algorithm 1:
+ * [-pi, pi] discretised uniformly; pi itself is -pi), cos and sin computed
+ * in double and rounded once. */
+OR_EXPORT void or_sample_dirs(int J, float* cs, float* sn) {
+    double step = (2.0 * M_PI) / (double)J;
+    for (int j = 0; j < J; ++j) {
+        double th = -M_PI + (double)j * step;
+        cs[j] = (float)cos(th);
+        sn[j] = (float)sin(th);
+    }
+}
+
+/* Orthonormal basis of the plane normal to z = (q - p)/|q - p| (Algorithm 1):
+ * alpha0 = e_k with k = argmin |z_k| (lowest k on ties), alpha1 = alpha0 minus
+ * its projection onto z, normalised, alpha2 = alpha1 x z.  Returns 0 (no
+ * samples) when |q - p|^2 is zero, subnormal-underflowed or not finite. */
+OR_EXPORT int or_sample_basis(const float* p, const float* q, float z[3], float a1[3], float a2[3]) {
+    float d[3];
+    d[0] = q[0] - p[0];
+    d[1] = q[1] - p[1];
+    d[2] = q[2] - p[2];
+    float n2 = ((d[0] * d[0]) + (d[1] * d[1])) + (d[2] * d[2]);
+    if (!(n2 > 0.0f) || !isfinite(n2)) return 0;
+    float nz = sqrtf(n2);
+    for (int k = 0; k < 3; ++k) z[k] = d[k] / nz;
+    int k0 = 0;
+    for (int k = 1; k < 3; ++k)
+        if (fabsf(z[k]) < fabsf(z[k0])) k0 = k;
+    /* alpha0 - (alpha0 . z) z with alpha0 = e_k0: alpha0 . z = z[k0] */
+    float t[3];
+    for (int k = 0; k < 3; ++k) {
+        float e = (k == k0) ? 1.0f : 0.0f;
+        float pz = z[k0] * z[k];
+        t[k] = e - pz;
+    }
+    float m2 = ((t[0] * t[0]) + (t[1] * t[1])) + (t[2] * t[2]);
+    float m = sqrtf(m2);
+    for (int k = 0; k < 3; ++k) a1[k] = t[k] / m;
+    /* alpha2 = alpha1 x z */
+    a2[0] = (a1[1] * z[2]) - (a1[2] * z[1]);
+    a2[1] = (a1[2] * z[0]) - (a1[0] * z[2]);
+    a2[2] = (a1[0] * z[1]) - (a1[1] * z[0]);
+    return 1;
+}
+
+/* Sample s = alpha1 cos(theta) + alpha2 sin(theta) on the great circle. */
+OR_EXPORT void or_sample_point(const float a1[3], const float a2[3], float c, float s, float out[3]) {
+    for (int k = 0; k < 3; ++k) {
+        float x = a1[k] * c;
+        float y = a2[k] * s;
+        out[k] = x + y;
+    }
+}
+
+/* Cell of a sample: only the closed southern hemisphere (s_z <= 0) votes
+ * (its antipodes name the same axes); projection from the north pole,
+ * (u, v) = (s_x, s_y) * (1 / (1 - s_z)) (Eq. (7)); cell index
+ * floor((u + 1) * G/2), clamped to [0, G-1] (u = 1 lies on the last cell's
+ * closed edge).  Returns -1 for a northern sample, else iy*G + ix. */
+OR_EXPORT long or_sample_cell(const float s[3], int G) {
+    if (!(s[2] <= 0.0f)) return -1;
+    float den = 1.0f - s[2];
+    float rinv = 1.0f / den;
+    float u = s[0] * rinv;
+    float v = s[1] * rinv;
+    float hg = 0.5f * (float)G;
+    float tu = (u + 1.0f) * hg;
+    float tv = (v + 1.0f) * hg;
+    long ix = (long)floorf(tu), iy = (long)floorf(tv);
+    if (ix < 0) ix = 0;
+    if (ix > G - 1) ix = G - 1;
+    if (iy < 0) iy = 0;
+    if (iy > G - 1) iy = G - 1;
+    return iy * G + ix;
+}
+
+/* Coarse accumulator by the literal sampling rule: every sample of every
+ * correspondence adds one vote to its cell (a circle can vote several times
+ * for one cell).  grid is G*G, zeroed here. */
+OR_EXPORT void or_sample_grid(const float* P, const float* Q, long n, int G, int J, uint32_t* grid) {
+    float* cs = (float*)malloc(sizeof(float) * (size_t)J);
+    float* sn = (float*)malloc(sizeof(float) * (size_t)J);
+    or_sample_dirs(J, cs, sn);
+    memset(grid, 0, sizeof(uint32_t) * (size_t)G * G);
+    for (long i = 0; i < n; ++i) {
+        float p[3], q[3], z[3], a1[3], a2[3];
+        gather(P, n, i, p);
+        gather(Q, n, i, q);
+        if (!or_sample_basis(p, q, z, a1, a2)) continue;
+        for (int j = 0; j < J; ++j) {
+            float s[3];
+            or_sample_point(a1, a2, cs[j], sn[j], s);
+            long c = or_sample_cell(s, G);
+            if (c >= 0) grid[c] += 1u;
+        }
+    }
+    free(cs);
+    free(sn);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -584,3 +584,162 @@ def test_angle_coarse_to_fine_consistency_and_accuracy(orc):
         assert d <= half * 1.01, (d, half)
         assert out["angle_fine_bin"] // F in {(out["angle_bin"] + dc) % B for dc in (-1, 0, 1)}
         assert out["angle_fine_votes"] >= 200 and out["gate"][:200].all()
+
+
+# ------------------------------------------------- literal sampling rule
+def test_sample_basis_is_orthonormal_and_follows_alpha0(orc):
+    """z is the unit direction of q - p; alpha1, alpha2 are orthonormal and
+    normal to z with alpha2 = alpha1 x z (so alpha1 x alpha2 = -z); alpha1
+    lies in the plane of z and the axis e_k of z's smallest component
+    (Algorithm 1's basis vector alpha0)."""
+    rng = np.random.default_rng(61)
+    for _ in range(200):
+        p, q = rng.uniform(-1, 1, 3).astype(np.float32), rng.uniform(-1, 1, 3).astype(np.float32)
+        z, a1, a2 = (x.astype(np.float64) for x in orc.sample_basis(p, q))
+        d = q.astype(np.float64) - p
+        assert np.allclose(z, d / np.linalg.norm(d), atol=3e-7)
+        for v in (a1, a2):
+            assert abs(np.linalg.norm(v) - 1) < 1e-6
+        assert abs(a1 @ z) < 1e-6 and abs(a2 @ z) < 1e-6 and abs(a1 @ a2) < 1e-6
+        assert np.allclose(np.cross(a1, a2), -z, atol=1e-6)
+        k = int(np.argmin(np.abs(d)))
+        e = np.zeros(3)
+        e[k] = 1
+        assert abs(a1 @ np.cross(e, z)) < 1e-6 and a1[k] > 0
+    assert orc.sample_basis([1, 2, 3], [1, 2, 3]) is None
+    assert orc.sample_basis([0, 0, 0], [np.inf, 0, 0]) is None
+
+
+def test_sample_points_walk_the_great_circle(orc):
+    """Samples lie on the unit sphere and on the great circle normal to
+    q - p, consecutive samples 2 pi / J apart, sample 0 at theta = -pi."""
+    rng = np.random.default_rng(62)
+    J = 96
+    for _ in range(20):
+        p, q = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        S = orc.sample_points(p, q, J).astype(np.float64)
+        z, a1, _ = orc.sample_basis(p, q)
+        assert np.allclose(np.linalg.norm(S, axis=0), 1, atol=1e-6)
+        assert np.max(np.abs(z.astype(np.float64) @ S)) < 1e-6
+        steps = np.arccos(np.clip(np.sum(S * np.roll(S, -1, axis=1), axis=0), -1, 1))
+        assert np.allclose(steps, 2 * math.pi / J, atol=2e-3 * 2 * math.pi / J)
+        assert np.allclose(S[:, 0], -a1, atol=1e-7)
+
+
+def test_sample_cell_is_the_projection(orc):
+    """A southern sample's cell contains its stereographic projection (Eq.
+    (7), in double), which lies on the projected circle with centre -(a,b)/c
+    and radius |d|/|c| (Sec. IV); northern samples cast no vote."""
+    rng = np.random.default_rng(63)
+    G, J = 64, 64
+    for _ in range(30):
+        p, q = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+        d = np.asarray(q, np.float32).astype(np.float64) - np.asarray(p, np.float32)
+        S = orc.sample_points(p, q, J)
+        for j in range(J):
+            s = S[:, j]
+            c = orc.sample_cell(s, G)
+            if s[2] > 0:
+                assert c == -1
+                continue
+            u, v = e7(s.astype(np.float64))
+            centre = -d[:2] / d[2]
+            assert abs(math.hypot(u - centre[0], v - centre[1]) - np.linalg.norm(d) / abs(d[2])) < \
+                2e-5 * np.linalg.norm(d) / abs(d[2])
+            tu, tv = (u + 1) * G / 2, (v + 1) * G / 2
+            if min(abs(tu - round(tu)), abs(tv - round(tv))) < 1e-4:
+                continue   # next to a cell edge: either side is the projection within rounding
+            ix, iy = min(int(math.floor(tu)), G - 1), min(int(math.floor(tv)), G - 1)
+            assert c == iy * G + ix, (u, v, c)
+
+
+@pytest.mark.parametrize("G,J", [(64, 256), (128, 1024)])
+def test_sample_vote_maps_by_hand(orc, G, J):
+    """d along e3: the circle is the equator, every sample lies on it (s_z = 0)
+    and votes for the cell of (cos, sin) of its angle on the unit circle; d
+    along e1: the southern half of the circle x = 0 projects onto the segment
+    u = 0, i.e. the column of cells starting at u = 0."""
+    Z = np.zeros((3, 1), np.float32)
+    g = orc.sample_grid(Z, np.array([[0], [0], [1]], np.float32), G, J)
+    assert g.sum() == J
+    cs, sn = orc.sample_dirs(J)
+    expect = np.zeros((G, G), np.int64)
+    for j in range(J):
+        # alpha1 = e1, alpha2 = e1 x e3 = -e2: the point is (cos, -sin, 0)
+        x, y = float(cs[j]), -float(sn[j])
+        ix = min(max(int(math.floor((x + 1) * G / 2)), 0), G - 1)
+        iy = min(max(int(math.floor((y + 1) * G / 2)), 0), G - 1)
+        expect[iy, ix] += 1
+    assert np.array_equal(g, expect)
+    g = orc.sample_grid(Z, np.array([[1], [0], [0]], np.float32), G, J)
+    cols = np.nonzero(g.sum(axis=0))[0]
+    assert list(cols) == [G // 2]
+    assert abs(int(g.sum()) - J // 2) <= 1
+
+
+def test_sample_grid_half_the_circle_and_invariants(orc):
+    """Each correspondence casts J/2 votes up to the samples on the equator
+    (half its great circle is southern); the grid is additive over a split of
+    the input and invariant under a permutation; degenerate pairs cast none."""
+    inst = synth.make_instance(300, 64)
+    G, J = 64, 512
+    total = 0
+    for i in range(40):
+        g = orc.sample_grid(inst.P[:, i:i + 1], inst.Q[:, i:i + 1], G, J)
+        assert abs(int(g.sum()) - J // 2) <= 1
+        total += int(g.sum())
+    g_all = orc.sample_grid(inst.P, inst.Q, G, J)
+    g_a = orc.sample_grid(inst.P[:, :120], inst.Q[:, :120], G, J)
+    g_b = orc.sample_grid(inst.P[:, 120:], inst.Q[:, 120:], G, J)
+    assert np.array_equal(g_all, g_a + g_b)
+    perm = np.random.default_rng(0).permutation(300)
+    assert np.array_equal(g_all, orc.sample_grid(inst.P[:, perm], inst.Q[:, perm], G, J))
+    assert orc.sample_grid(inst.P[:, :40], inst.P[:, :40], G, J).sum() == 0
+
+
+def test_sample_rule_tracks_the_cell_rule(orc):
+    """Densely sampled (J = 16 G), the cells a circle's samples land in and
+    the cells the per-cell rule votes agree up to one cell: every sampled cell
+    touches a voted one, and every voted cell inside the open disk touches a
+    sampled one (on the rim the per-cell rule also counts arcs that run just
+    outside the disk, which no southern sample reaches)."""
+    rng = np.random.default_rng(65)
+    G, J = 64, 1024
+    t = -1 + 2 * np.arange(G + 1) / G
+    far = np.maximum(np.abs(t[:-1]), np.abs(t[1:]))
+    inside = (far[None, :] ** 2 + far[:, None] ** 2) < 1
+    for _ in range(25):
+        p = rng.uniform(-1, 1, (3, 1)).astype(np.float32)
+        q = rng.uniform(-1, 1, (3, 1)).astype(np.float32)
+        gs = orc.sample_grid(p, q, G, J) > 0
+        gc = orc.coarse_grid(p, q, G) > 0
+        def dil(m):
+            out = m.copy()
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    out |= np.roll(np.roll(m, dy, 0), dx, 1)
+            return out
+        assert not (gs & ~dil(gc)).any()
+        assert not (gc & inside & ~dil(gs)).any()
+
+
+def test_sample_rule_noise_free_peak(orc):
+    """Noise-free inliers of a rotation about r: the sampled accumulator's
+    peak cell holds the projection of r (within one cell)."""
+    rng = np.random.default_rng(66)
+    G, J = 128, 1024
+    for _ in range(3):
+        r = rng.normal(size=3)
+        r /= np.linalg.norm(r)
+        if r[2] > 0:
+            r = -r
+        K = np.array([[0, -r[2], r[1]], [r[2], 0, -r[0]], [-r[1], r[0], 0]])
+        R = np.eye(3) + math.sin(1.1) * K + (1 - math.cos(1.1)) * K @ K
+        P = rng.uniform(-1, 1, (3, 300)).astype(np.float32)
+        Q = (R @ P.astype(np.float64)).astype(np.float32)
+        Q[:, 200:] = rng.uniform(-1, 1, (3, 100)).astype(np.float32)
+        g = orc.sample_grid(P, Q, G, J)
+        pk = int(np.argmax(g))
+        u, v = e7(r)
+        ix, iy = int((u + 1) * G / 2), int((v + 1) * G / 2)
+        assert abs(pk % G - ix) <= 1 and abs(pk // G - iy) <= 1
