@@ -119,6 +119,44 @@ def bench_c2f(aor, L, C, torch, P, Q, inst, reps: int) -> dict:
             "n_inliers": res["n_inliers"], "status": int(st)}
 
 
+SAMPLE_OPS = 19   # per southern sample: point 9, projection 4, cell 6 (binary32 operations as written)
+
+
+def bench_sample_rule(aor, L, C, torch, P, Q, inst, reps: int) -> dict:
+    """The headline workload with the literal sampling rule of Algorithm 1 in
+    place of the per-cell rule (J = 8 G = 8192 samples per circle)."""
+    from paper_2502_06337_amd import _lib
+    prm = aor.SolveParams(grid=G, refine_grid=M, angle_bins=B, inlier_thresh=0.05, vote_rule=1)
+    res, _, st = aor.est_rotation(P, Q, prm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        aor.est_rotation(P, Q, prm)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    cprm = _lib._params(prm)
+    ms = (C.c_float * 8)()
+    nst = C.c_uint32(0)
+    stream = torch.cuda.current_stream(P.device).cuda_stream
+    vote_ms = []
+    for _ in range(3):
+        if L.aoresp_stage_times_dev(P.data_ptr(), Q.data_ptr(), P.shape[1], C.byref(cprm), ms, C.byref(nst),
+                                    stream) != 0:
+            raise RuntimeError("stage timing failed")
+        vote_ms.append(ms[STAGES.index("coarse_vote")])
+    t_vote = float(np.mean(vote_ms))
+    votes = int(aor.solve_debug(P, Q, prm)["grid"].to(torch.int64).sum().item())
+    ach = SAMPLE_OPS * votes / (t_vote * 1e-3) / 1e12
+    return {"workload": "headline input, literal sampling rule, J = 8192 samples per circle",
+            "ms_per_solve": round(dt * 1e3, 4), "Mcorr_s": round(P.shape[1] / dt / 1e6, 2),
+            "sample_vote_ms": round(t_vote, 4), "votes": votes,
+            "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
+                         "unit": "TFLOP/s", "frac": round(ach / ALU_PEAK_TFLOPS, 4), "ops_per_vote": SAMPLE_OPS},
+            "rotation_error_deg": round(rotation_error_deg(inst.R_gt[0], res["R"]), 5),
+            "rotation_error_deg_ls": round(rotation_error_deg(inst.R_gt[0], res["R_ls"]), 5),
+            "axis_votes": res["axis_votes"], "n_inliers": res["n_inliers"], "status": int(st)}
+
+
 def bench_topk(aor, synth, torch, reps: int) -> dict:
     """Multi-rotation workload: n = 1e6, three rotations with 10% inliers
     each, 70% outliers, sigma = 0.01; top-3 peaks with suppression radius 5,
@@ -244,6 +282,8 @@ def main() -> int:
     ap.add_argument("--batch-reps", type=int, default=3, help="batched workload repetitions (0 = skip)")
     ap.add_argument("--topk-reps", type=int, default=5, help="multi-rotation workload repetitions (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=1.0, help="served stream length (0 = skip)")
+    ap.add_argument("--sample-reps", type=int, default=5,
+                    help="literal sampling rule repetitions on the headline input (0 = skip)")
     ap.add_argument("--c2f-reps", type=int, default=10,
                     help="coarse-to-fine angle voting repetitions on the headline input (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -354,6 +394,8 @@ def main() -> int:
         "cpu_baseline": cpu,
         "stages_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_avg)},
         "tuning": tuning,
+        "sample_rule": bench_sample_rule(aor, L, C, torch, P, Q, inst, args.sample_reps)
+        if args.sample_reps > 0 else None,
         "angle_c2f": bench_c2f(aor, L, C, torch, P, Q, inst, args.c2f_reps) if args.c2f_reps > 0 else None,
         "topk": bench_topk(aor, synth, torch, args.topk_reps) if args.topk_reps > 0 else None,
         "batch": bench_batch(aor, synth, torch, args.batch_reps) if args.batch_reps > 0 else None,

@@ -70,6 +70,10 @@ typedef struct {
     uint32_t angle_refine;   /* F: 0 or 1 = angle from the B-bin histogram; else in [2, 256] with
                                 B*F <= 65536: a second histogram over B*F bins, read on the 3F fine bins
                                 of coarse bins k-1, k, k+1 around the coarse peak k, gives the angle */
+    uint32_t vote_rule;      /* coarse accumulator: 0 = per-cell rule (a cell counts the circles crossing it,
+                                Fig. 3(c)); 1 = literal sampling rule of Algorithm 1 (J samples per great
+                                circle, each southern sample adds one vote to the cell of its projection) */
+    uint32_t circle_samples; /* J for vote_rule 1: 0 -> 8*G (plane step at most h/2); else in [4, 65536] */
 } aoresp_params;
 
 /* Result of one rotation. */

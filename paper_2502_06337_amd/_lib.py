@@ -30,7 +30,8 @@ class AorespError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("grid", C.c_uint32), ("refine_grid", C.c_uint32), ("refine_halfwin", C.c_uint32),
                 ("angle_bins", C.c_uint32), ("nms_radius", C.c_uint32), ("inlier_thresh", C.c_float),
-                ("angle_gate", C.c_uint32), ("angle_refine", C.c_uint32)]
+                ("angle_gate", C.c_uint32), ("angle_refine", C.c_uint32), ("vote_rule", C.c_uint32),
+                ("circle_samples", C.c_uint32)]
 
 
 class Result(C.Structure):
@@ -131,10 +132,12 @@ class SolveParams:
     inlier_thresh: float = 0.0
     angle_gate: int = 0
     angle_refine: int = 0
+    vote_rule: int = 0
+    circle_samples: int = 0
 
     def c(self) -> Params:
         return Params(self.grid, self.refine_grid, self.refine_halfwin, self.angle_bins, self.nms_radius,
-                      self.inlier_thresh, self.angle_gate, self.angle_refine)
+                      self.inlier_thresh, self.angle_gate, self.angle_refine, self.vote_rule, self.circle_samples)
 
 
 def _params(prm) -> Params:

@@ -48,6 +48,8 @@ aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams&
     rp.tau = p.inlier_thresh > 0.0f ? p.inlier_thresh : 0.05f;
     rp.gate = (int)p.angle_gate;
     rp.F = p.angle_refine > 1 ? (int)p.angle_refine : 1;
+    rp.rule = (int)p.vote_rule;
+    rp.J = p.circle_samples ? (int)p.circle_samples : 8 * rp.G;
     if (!is_pow2((uint32_t)rp.G) || rp.G < 64 || rp.G > 4096) return AORESP_EINVAL;
     if (rp.M != 0 && (!is_pow2((uint32_t)rp.M) || rp.M < 8 || rp.M > 128 || (int64_t)rp.G * rp.M > 262144))
         return AORESP_EINVAL;
@@ -57,6 +59,8 @@ aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams&
     if (!std::isfinite(rp.tau)) return AORESP_EINVAL;
     if (p.angle_gate > 1) return AORESP_EINVAL;
     if (p.angle_refine > 256 || (int64_t)rp.B * rp.F > 65536) return AORESP_EINVAL;
+    if (p.vote_rule > 1) return AORESP_EINVAL;
+    if (p.circle_samples > 65536 || (p.circle_samples != 0 && p.circle_samples < 4)) return AORESP_EINVAL;
     return AORESP_OK;
 }
 
@@ -268,6 +272,15 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
             if (flds > 160 * 1024) return AORESP_EINVAL;
             if (flds > plan.fhist_lds) plan.fhist_lds = flds;
         }
+        I.rule = rp.rule;
+        I.J = rp.J;
+        if (rp.rule == 1) {
+            const AngleTables* sd = angle_tables(ctx, rp.J);   // cos, sin of -pi + j 2pi/J
+            if (!sd) return AORESP_ENOMEM;
+            I.scs = sd->tc;
+            I.ssn = sd->ts;
+            if (rp.J <= kSampleLdsMax && (size_t)rp.J * 8 > plan.sample_lds) plan.sample_lds = (size_t)rp.J * 8;
+        }
         // coarse-vote work split: forced (tuner candidate), tuned for (G, n), or default
         const Tuning tu = force ? *force : tuning_for(ctx, rp.G, n);
         const int bw = coarse_band_width(rp.G, tu.tile_cells);
@@ -279,7 +292,13 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         chunk = (chunk + kVoteThreads - 1) / kVoteThreads * kVoteThreads;
         if (chunk < kVoteThreads) chunk = kVoteThreads;
         if (chunk > kMaxItemArcs) chunk = kMaxItemArcs;   // 16-bit tile counters
-        for (int mode = 0; mode < 2; ++mode)
+        if (rp.rule == 1) {
+            for (int64_t i0 = 0; i0 < n; i0 += kSampleChunk) {
+                int64_t i1 = i0 + kSampleChunk < n ? i0 + kSampleChunk : n;
+                plan.sample_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
+            }
+        }
+        for (int mode = 0; mode < 2 && rp.rule == 0; ++mode)
             for (int band = 0; band < nbands; ++band)
                 for (int64_t i0 = 0; i0 < n; i0 += chunk) {
                     int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
@@ -320,7 +339,7 @@ size_t plan_blob_bytes(const Plan& plan) {
     const size_t b_inst = plan.insts.size() * sizeof(Inst);
     const size_t o_vote = (b_inst + 255) / 256 * 256;
     return o_vote + (plan.vote_items.size() + plan.cell_items.size() + plan.corr_items.size() +
-                     plan.list_items.size()) * sizeof(int4) + 16;
+                     plan.list_items.size() + plan.sample_items.size()) * sizeof(int4) + 16;
 }
 
 aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const float* P, const float* Q,
@@ -352,6 +371,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     const size_t o_cell = o_vote + plan.vote_items.size() * sizeof(int4);
     const size_t o_corr = o_cell + plan.cell_items.size() * sizeof(int4);
     const size_t o_list = o_corr + plan.corr_items.size() * sizeof(int4);
+    const size_t o_samp = o_list + plan.list_items.size() * sizeof(int4);
     const size_t total = plan_blob_bytes(plan);
     if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
     if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
@@ -365,6 +385,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
         std::memcpy(hb + o_corr, plan.corr_items.data(), plan.corr_items.size() * sizeof(int4));
     if (!plan.list_items.empty())
         std::memcpy(hb + o_list, plan.list_items.data(), plan.list_items.size() * sizeof(int4));
+    if (!plan.sample_items.empty())
+        std::memcpy(hb + o_samp, plan.sample_items.data(), plan.sample_items.size() * sizeof(int4));
     AOR_HIP(hipMemcpyAsync(w.plan.ptr, hb, total, hipMemcpyHostToDevice, s));
     char* db = w.plan.as<char>();
     const Inst* insts = reinterpret_cast<const Inst*>(db);
@@ -372,6 +394,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     const int4* cell_items = reinterpret_cast<const int4*>(db + o_cell);
     const int4* corr_items = reinterpret_cast<const int4*>(db + o_corr);
     const int4* list_items = reinterpret_cast<const int4*>(db + o_list);
+    const int4* sample_items = reinterpret_cast<const int4*>(db + o_samp);
 
     ArcRecs R{w.abc.as<float4>(), w.colp.as<int4>(), w.rowp.as<int4>(), w.geo.as<int4>()};
     char* ob = w.out.as<char>();
@@ -400,6 +423,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     mark(1);
     launch_vote(R, insts, vote_items, (int)plan.vote_items.size(), counter, w.grid.as<uint32_t>(), err,
                 ctx->cu_count, s);
+    launch_sample_vote(P, Q, N, insts, sample_items, (int)plan.sample_items.size(), w.grid.as<uint32_t>(),
+                       plan.sample_lds, s);
     mark(2);
     for (int t = 0; t < plan.max_npk; ++t) {
         launch_peak(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), stt, t, keys, s);

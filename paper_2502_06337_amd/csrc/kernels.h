@@ -72,6 +72,10 @@ struct Inst {
     const float* fth;
     const float* fct;
     const float* fst;
+    int32_t rule;         // coarse accumulator rule: 0 per-cell rule, 1 literal sampling rule
+    int32_t J;            // samples per great circle (rule 1)
+    const float* scs;     // sample directions: cos, sin of -pi + j 2pi/J (rule 1)
+    const float* ssn;
 };
 
 struct FineWin {
@@ -127,6 +131,15 @@ void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int ni
                       uint32_t* fine_arena, uint32_t* err, int maxM, hipStream_t s);
 void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                       hipStream_t s);
+// Literal sampling rule of Algorithm 1 (instances with rule 1): every one of
+// J samples of each great circle that lies on the closed southern hemisphere
+// adds one vote to the coarse cell of its projection.  Items: (instance,
+// first, last correspondence); a block's sample directions are staged in LDS
+// when J <= kSampleLdsMax (lds_bytes = 8 J of the largest such J, else 0).
+constexpr int kSampleLdsMax = 16384;
+constexpr int kSampleChunk = 1024;
+void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
+                        uint32_t* grid_arena, size_t lds_bytes, hipStream_t s);
 void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
                        const PeakState* st, uint32_t* hist_arena, size_t lds_bytes, hipStream_t s);
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,

@@ -786,6 +786,112 @@ __global__ __launch_bounds__(1024) void k_fine_peak(const uint32_t* __restrict__
 }
 
 // --------------------------------------------------------------------------
+// Literal sampling rule (Algorithm 1's inner loop; selectable alternative to
+// the per-cell rule of the coarse vote)
+// --------------------------------------------------------------------------
+
+// Frame of the great circle of (p, q): z = (q - p)/|q - p|, alpha1 = e_k minus
+// its projection onto z, normalised (k = index of z's smallest component,
+// lowest on ties), alpha2 = alpha1 x z.  False when |q - p|^2 is zero or not
+// finite (no samples).  Every value is one rounded binary32 operation in the
+// order written; square root and division are correctly rounded.
+__device__ __forceinline__ bool sample_frame(const float* p, const float* q, float* a1, float* a2) {
+    const float d0 = q[0] - p[0], d1 = q[1] - p[1], d2 = q[2] - p[2];
+    const float n2 = ((d0 * d0) + (d1 * d1)) + (d2 * d2);
+    if (!(n2 > 0.0f) || !isfinite(n2)) return false;
+    const float nz = sqrtf(n2);
+    const float z[3] = {d0 / nz, d1 / nz, d2 / nz};
+    int k0 = 0;
+    if (fabsf(z[1]) < fabsf(z[k0])) k0 = 1;
+    if (fabsf(z[2]) < fabsf(z[k0])) k0 = 2;
+    const float zk = z[k0];
+    float t[3];
+    for (int k = 0; k < 3; ++k) {
+        const float e = (k == k0) ? 1.0f : 0.0f;
+        const float pz = zk * z[k];
+        t[k] = e - pz;
+    }
+    const float m = sqrtf(((t[0] * t[0]) + (t[1] * t[1])) + (t[2] * t[2]));
+    for (int k = 0; k < 3; ++k) a1[k] = t[k] / m;
+    a2[0] = (a1[1] * z[2]) - (a1[2] * z[1]);
+    a2[1] = (a1[2] * z[0]) - (a1[0] * z[2]);
+    a2[2] = (a1[0] * z[1]) - (a1[1] * z[0]);
+    return true;
+}
+
+// Cell of sample s = alpha1 cos + alpha2 sin, or -1 on the open northern
+// hemisphere: projection from the north pole (Eq. (7)) as
+// (s_x, s_y) * (1 / (1 - s_z)), cell floor((u + 1) G/2) clamped to [0, G-1].
+__device__ __forceinline__ int sample_cell(const float* a1, const float* a2, float c, float sn, int G, float hg) {
+    const float s0 = (a1[0] * c) + (a2[0] * sn);
+    const float s1 = (a1[1] * c) + (a2[1] * sn);
+    const float s2 = (a1[2] * c) + (a2[2] * sn);
+    if (!(s2 <= 0.0f)) return -1;
+    const float rinv = 1.0f / (1.0f - s2);
+    const float u = s0 * rinv, v = s1 * rinv;
+    int ix = (int)floorf((u + 1.0f) * hg);
+    int iy = (int)floorf((v + 1.0f) * hg);
+    ix = ix < 0 ? 0 : (ix > G - 1 ? G - 1 : ix);
+    iy = iy < 0 ? 0 : (iy > G - 1 ? G - 1 : iy);
+    return iy * G + ix;
+}
+
+// One wave walks one circle at a time, 64 consecutive samples per step.
+// Consecutive samples mostly share a cell, so each run of equal cells along
+// the wave is added by its first lane with one atomic.
+__device__ __forceinline__ void sample_circles(const float* __restrict__ P, const float* __restrict__ Q, int64_t N,
+                                               const Inst& I, int64_t l0, int64_t l1, const float* cs,
+                                               const float* sn, uint32_t* __restrict__ grid) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int J = I.J, G = I.G;
+    const float hg = 0.5f * (float)G;
+    for (int64_t li = l0 + wave; li < l1; li += nw) {
+        const int64_t i = I.off + li;
+        const float p[3] = {P[i], P[N + i], P[2 * N + i]};
+        const float q[3] = {Q[i], Q[N + i], Q[2 * N + i]};
+        float a1[3], a2[3];
+        if (!sample_frame(p, q, a1, a2)) continue;   // same inputs on every lane: uniform
+        for (int j0 = 0; j0 < J; j0 += 64) {
+            const int j = j0 + lane;
+            int cell = -1;
+            if (j < J) cell = sample_cell(a1, a2, cs[j], sn[j], G, hg);
+            const int prev = __shfl_up(cell, 1);
+            const bool head = lane == 0 || prev != cell;
+            const unsigned long long heads = __ballot(head);
+            if (head && cell >= 0) {
+                const unsigned long long later = lane == 63 ? 0ull : (heads >> (lane + 1));
+                const uint32_t len = later ? (uint32_t)__builtin_ctzll(later) + 1u : (uint32_t)(64 - lane);
+                atomicAdd(&grid[cell], len);
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sample_vote(const float* __restrict__ P, const float* __restrict__ Q,
+                                                      int64_t N, const Inst* __restrict__ insts,
+                                                      const int4* __restrict__ items,
+                                                      uint32_t* __restrict__ grid_arena) {
+    extern __shared__ __align__(16) uint32_t sm[];
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
+    uint32_t* grid = grid_arena + I.grid_off;
+    const int J = I.J;
+    if (J <= kSampleLdsMax) {
+        float* cs = reinterpret_cast<float*>(sm);
+        float* sn = cs + J;
+        for (int j = threadIdx.x; j < J; j += blockDim.x) {
+            cs[j] = I.scs[j];
+            sn[j] = I.ssn[j];
+        }
+        __syncthreads();
+        sample_circles(P, Q, N, I, wi.y, wi.z, cs, sn, grid);
+    } else {
+        sample_circles(P, Q, N, I, wi.y, wi.z, I.scs, I.ssn, grid);
+    }
+}
+
+// --------------------------------------------------------------------------
 // Angle histogram (Sec. IV-B)
 // --------------------------------------------------------------------------
 
@@ -1319,6 +1425,7 @@ void init_kernel_attributes() {
     set_lds_limit((const void*)k_fine_vote);
     set_lds_limit((const void*)k_angle_hist);
     set_lds_limit((const void*)k_angle_fine_hist);
+    set_lds_limit((const void*)k_sample_vote);
 }
 
 void launch_zero_list(const ZeroList& zl, hipStream_t s) {
@@ -1374,6 +1481,13 @@ void launch_fine_vote(ArcRecs recs, const Inst* insts, const int4* items, int ni
 void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, PeakState* st, int slot,
                       hipStream_t s) {
     hipLaunchKernelGGL(k_fine_peak, dim3((unsigned)ninst), dim3(1024), 0, s, fine_arena, insts, st, slot);
+}
+
+void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
+                        uint32_t* grid_arena, size_t lds_bytes, hipStream_t s) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(k_sample_vote, dim3((unsigned)nitems), dim3(1024), lds_bytes, s, P, Q, N, insts, items,
+                       grid_arena);
 }
 
 void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,

@@ -16,6 +16,7 @@ struct ResolvedParams {
     int G, M, w, B, rad;
     float tau;
     int gate, F;   // angle gate on/off; fine angle factor (1 = none)
+    int rule, J;   // coarse accumulator rule (0 per-cell, 1 sampling); samples per circle
 };
 
 aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams& rp);
@@ -81,7 +82,7 @@ struct Workspace {
 // A batch laid out for the kernels.
 struct Plan {
     std::vector<Inst> insts;
-    std::vector<int4> vote_items, cell_items, corr_items, list_items;
+    std::vector<int4> vote_items, cell_items, corr_items, list_items, sample_items;
     int64_t N = 0;
     size_t grid_cells = 0, fine_cells = 0, hist_cells = 0;
     size_t fhist_cells = 0;    // fine-angle windows, after the histograms in the same arena
@@ -89,6 +90,7 @@ struct Plan {
     int max_npk = 0, maxM = 0;
     size_t hist_lds = 0;
     size_t fhist_lds = 0;      // 0: no instance refines its angle
+    size_t sample_lds = 0;     // LDS of the sampling vote (sample directions staged per block)
 };
 
 // Work split of the coarse vote for one (G, n bucket): LDS tile cells and

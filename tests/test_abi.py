@@ -57,7 +57,8 @@ def test_strerror(lib):
 
 @pytest.mark.parametrize("field,val", [("grid", 100), ("grid", 32), ("grid", 8192), ("refine_grid", 3),
                                        ("refine_grid", 256), ("angle_bins", 1), ("angle_bins", 9000),
-                                       ("angle_gate", 2), ("angle_refine", 257), ("angle_refine", 200)])
+                                       ("angle_gate", 2), ("angle_refine", 257), ("angle_refine", 200),
+                                       ("vote_rule", 2), ("circle_samples", 3), ("circle_samples", 65537)])
 def test_invalid_params_rejected_on_host(lib, field, val):
     from paper_2502_06337_amd import _lib
     prm = _lib.SolveParams(grid=256, angle_bins=360)
