@@ -215,7 +215,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
                               const Tuning* force, Plan& plan) {
     plan = Plan();
     plan.insts.resize(ninst);
-    std::vector<std::pair<double, int4>> votes;
+    std::vector<std::pair<double, int4>> votes, samples;
     size_t hist_lds = 0;
     for (int b = 0; b < ninst; ++b) {
         const ResolvedParams& rp = rps[b];
@@ -279,7 +279,20 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
             if (!sd) return AORESP_ENOMEM;
             I.scs = sd->tc;
             I.ssn = sd->ts;
-            if (rp.J <= kSampleLdsMax && (size_t)rp.J * 8 > plan.sample_lds) plan.sample_lds = (size_t)rp.J * 8;
+            size_t slds = 0;
+            sample_layout(rp.G, rp.J, I.sbw, I.sdir_lds, slds);
+            I.snb = rp.G / I.sbw;
+            // circles per band item: at most 32 chunks, and at most 2^27 partial cells per instance
+            int64_t maxch = ((int64_t)1 << 27) / ((int64_t)rp.G * rp.G);
+            maxch = maxch < 1 ? 1 : (maxch > 32 ? 32 : maxch);
+            int64_t ch = (n + maxch - 1) / maxch;
+            ch = ch < 2048 ? 2048 : (ch + 15) / 16 * 16;
+            I.schunk = (int32_t)ch;
+            I.ssetup_off = (int64_t)plan.sample_recs;
+            plan.sample_recs += (size_t)n;
+            I.spart_off = (int64_t)plan.sample_part;
+            plan.sample_part += (size_t)((n + ch - 1) / ch) * rp.G * rp.G;
+            if (slds > plan.sample_lds) plan.sample_lds = slds;
         }
         // coarse-vote work split: forced (tuner candidate), tuned for (G, n), or default
         const Tuning tu = force ? *force : tuning_for(ctx, rp.G, n);
@@ -293,10 +306,18 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         if (chunk < kVoteThreads) chunk = kVoteThreads;
         if (chunk > kMaxItemArcs) chunk = kMaxItemArcs;   // 16-bit tile counters
         if (rp.rule == 1) {
-            for (int64_t i0 = 0; i0 < n; i0 += kSampleChunk) {
-                int64_t i1 = i0 + kSampleChunk < n ? i0 + kSampleChunk : n;
-                plan.sample_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
+            for (int64_t i0 = 0; i0 < n; i0 += kSampleSetupChunk) {
+                int64_t i1 = i0 + kSampleSetupChunk < n ? i0 + kSampleSetupChunk : n;
+                plan.sample_setup_items.push_back(make_int4(b, (int)i0, (int)i1, 0));
             }
+            // band items, central bands (more samples) first
+            for (int band = 0; band < I.snb; ++band)
+                for (int64_t i0 = 0; i0 < n; i0 += I.schunk) {
+                    int64_t i1 = i0 + I.schunk < n ? i0 + I.schunk : n;
+                    double c = (band + 0.5) * I.sbw / (double)rp.G * 2.0 - 1.0;
+                    double share = std::sqrt(std::max(0.05, 1.0 - c * c));
+                    samples.push_back({share * (double)(i1 - i0), make_int4(b, band, (int)i0, (int)i1)});
+                }
         }
         for (int mode = 0; mode < 2 && rp.rule == 0; ++mode)
             for (int band = 0; band < nbands; ++band)
@@ -328,6 +349,9 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
                      [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
     plan.vote_items.reserve(votes.size());
     for (auto& v : votes) plan.vote_items.push_back(v.second);
+    std::stable_sort(samples.begin(), samples.end(),
+                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
+    for (auto& v : samples) plan.sample_items.push_back(v.second);
     plan.N = off[ninst];
     plan.hist_lds = hist_lds;
     return AORESP_OK;
@@ -339,7 +363,8 @@ size_t plan_blob_bytes(const Plan& plan) {
     const size_t b_inst = plan.insts.size() * sizeof(Inst);
     const size_t o_vote = (b_inst + 255) / 256 * 256;
     return o_vote + (plan.vote_items.size() + plan.cell_items.size() + plan.corr_items.size() +
-                     plan.list_items.size() + plan.sample_items.size()) * sizeof(int4) + 16;
+                     plan.list_items.size() + plan.sample_setup_items.size() + plan.sample_items.size()) *
+                        sizeof(int4) + 16;
 }
 
 aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const float* P, const float* Q,
@@ -364,6 +389,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
     if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
     if ((st = w.lsum.ensure((plan.corr_items.size() + 1) * kLsWords * sizeof(double))) != AORESP_OK) return st;
+    if ((st = w.srec.ensure(plan.sample_recs * kSampleRec * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.spart.ensure(plan.sample_part * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
@@ -371,7 +398,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     const size_t o_cell = o_vote + plan.vote_items.size() * sizeof(int4);
     const size_t o_corr = o_cell + plan.cell_items.size() * sizeof(int4);
     const size_t o_list = o_corr + plan.corr_items.size() * sizeof(int4);
-    const size_t o_samp = o_list + plan.list_items.size() * sizeof(int4);
+    const size_t o_sset = o_list + plan.list_items.size() * sizeof(int4);
+    const size_t o_samp = o_sset + plan.sample_setup_items.size() * sizeof(int4);
     const size_t total = plan_blob_bytes(plan);
     if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
     if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
@@ -385,6 +413,8 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
         std::memcpy(hb + o_corr, plan.corr_items.data(), plan.corr_items.size() * sizeof(int4));
     if (!plan.list_items.empty())
         std::memcpy(hb + o_list, plan.list_items.data(), plan.list_items.size() * sizeof(int4));
+    if (!plan.sample_setup_items.empty())
+        std::memcpy(hb + o_sset, plan.sample_setup_items.data(), plan.sample_setup_items.size() * sizeof(int4));
     if (!plan.sample_items.empty())
         std::memcpy(hb + o_samp, plan.sample_items.data(), plan.sample_items.size() * sizeof(int4));
     AOR_HIP(hipMemcpyAsync(w.plan.ptr, hb, total, hipMemcpyHostToDevice, s));
@@ -394,6 +424,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     const int4* cell_items = reinterpret_cast<const int4*>(db + o_cell);
     const int4* corr_items = reinterpret_cast<const int4*>(db + o_corr);
     const int4* list_items = reinterpret_cast<const int4*>(db + o_list);
+    const int4* sample_setup_items = reinterpret_cast<const int4*>(db + o_sset);
     const int4* sample_items = reinterpret_cast<const int4*>(db + o_samp);
 
     ArcRecs R{w.abc.as<float4>(), w.colp.as<int4>(), w.rowp.as<int4>(), w.geo.as<int4>()};
@@ -423,8 +454,9 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     mark(1);
     launch_vote(R, insts, vote_items, (int)plan.vote_items.size(), counter, w.grid.as<uint32_t>(), err,
                 ctx->cu_count, s);
-    launch_sample_vote(P, Q, N, insts, sample_items, (int)plan.sample_items.size(), w.grid.as<uint32_t>(),
-                       plan.sample_lds, s);
+    launch_sample_vote(P, Q, N, insts, sample_setup_items, (int)plan.sample_setup_items.size(), sample_items,
+                       (int)plan.sample_items.size(), cell_items, (int)plan.cell_items.size(), w.srec.as<uint32_t>(),
+                       w.spart.as<uint32_t>(), w.grid.as<uint32_t>(), plan.sample_lds, s);
     mark(2);
     for (int t = 0; t < plan.max_npk; ++t) {
         launch_peak(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), stt, t, keys, s);
@@ -562,6 +594,8 @@ aoresp_status reserve_plan(Workspace& w, const Plan& plan) {
     if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
     if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
     if ((st = w.lsum.ensure((plan.corr_items.size() + 1) * kLsWords * sizeof(double))) != AORESP_OK) return st;
+    if ((st = w.srec.ensure(plan.sample_recs * kSampleRec * 4 + 4)) != AORESP_OK) return st;
+    if ((st = w.spart.ensure(plan.sample_part * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
     const size_t total = plan_blob_bytes(plan);
     if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
@@ -575,7 +609,7 @@ void release_workspace(Workspace& w) {
     if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
     w.cap_stream = nullptr;
     DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.out,
-                      &w.icount, &w.lsum, &w.plan, &w.P, &w.Q, &w.masks};
+                      &w.icount, &w.lsum, &w.srec, &w.spart, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
     HostBuf* hb[] = {&w.h_plan, &w.h_out};
     for (HostBuf* b : hb) {

@@ -76,6 +76,11 @@ struct Inst {
     int32_t J;            // samples per great circle (rule 1)
     const float* scs;     // sample directions: cos, sin of -pi + j 2pi/J (rule 1)
     const float* ssn;
+    int32_t sbw, snb;     // rule 1: rows per band tile, bands
+    int32_t sdir_lds;     // rule 1: sample directions staged in LDS
+    int32_t schunk;       // rule 1: circles per band item
+    int64_t ssetup_off;   // rule 1: first circle record
+    int64_t spart_off;    // rule 1: u32 offset of its partial tiles (chunks x bands x sbw*G)
 };
 
 struct FineWin {
@@ -133,13 +138,23 @@ void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, 
                       hipStream_t s);
 // Literal sampling rule of Algorithm 1 (instances with rule 1): every one of
 // J samples of each great circle that lies on the closed southern hemisphere
-// adds one vote to the coarse cell of its projection.  Items: (instance,
-// first, last correspondence); a block's sample directions are staged in LDS
-// when J <= kSampleLdsMax (lds_bytes = 8 J of the largest such J, else 0).
-constexpr int kSampleLdsMax = 16384;
-constexpr int kSampleChunk = 1024;
-void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
-                        uint32_t* grid_arena, size_t lds_bytes, hipStream_t s);
+// adds one vote to the coarse cell of its projection.  Three launches: a
+// per-circle record (frame, window of southern sample indices, 64 checkpoint
+// rows) over setup items (instance, first, last circle); the band pass over
+// band items (instance, band, first, last circle), each accumulating one band
+// of kSampleTile cells in LDS and storing it to its slot of the partial arena
+// (chunk-major, kSampleTile-cell tiles); and the reduction over cell items
+// (instance, first, last cell) that writes the instance's grid.
+constexpr int kSampleTile = 32768;    // u32 counters per band tile (128 KiB of LDS), or the whole grid if smaller
+constexpr int kSampleRec = 40;        // u32 words per circle record
+constexpr int kSampleSetupChunk = 1024;
+// Band tile rows (a power of two), whether the sample directions are staged
+// in LDS beside the tile (when both fit in 160 KiB), and the LDS bytes of a
+// block.
+void sample_layout(int G, int J, int& bw, int& dirs_in_lds, size_t& lds_bytes);
+void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* setup_items,
+                        int nsetup, const int4* band_items, int nband, const int4* cell_items, int ncell,
+                        uint32_t* recs, uint32_t* part, uint32_t* grid_arena, size_t lds_bytes, hipStream_t s);
 void launch_angle_hist(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
                        const PeakState* st, uint32_t* hist_arena, size_t lds_bytes, hipStream_t s);
 void launch_angle_peak(const uint32_t* hist_arena, const Inst* insts, int ninst, PeakState* st, int slot,

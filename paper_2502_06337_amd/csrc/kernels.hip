@@ -819,75 +819,208 @@ __device__ __forceinline__ bool sample_frame(const float* p, const float* q, flo
     return true;
 }
 
-// Cell of sample s = alpha1 cos + alpha2 sin, or -1 on the open northern
+// Cell of sample s = alpha1 cos + alpha2 sin, or false on the open northern
 // hemisphere: projection from the north pole (Eq. (7)) as
 // (s_x, s_y) * (1 / (1 - s_z)), cell floor((u + 1) G/2) clamped to [0, G-1].
-__device__ __forceinline__ int sample_cell(const float* a1, const float* a2, float c, float sn, int G, float hg) {
+__device__ __forceinline__ bool sample_cell(const float* a1, const float* a2, float c, float sn, int G, float hg,
+                                            int& ix, int& iy) {
     const float s0 = (a1[0] * c) + (a2[0] * sn);
     const float s1 = (a1[1] * c) + (a2[1] * sn);
     const float s2 = (a1[2] * c) + (a2[2] * sn);
-    if (!(s2 <= 0.0f)) return -1;
+    if (!(s2 <= 0.0f)) return false;
     const float rinv = 1.0f / (1.0f - s2);
     const float u = s0 * rinv, v = s1 * rinv;
-    int ix = (int)floorf((u + 1.0f) * hg);
-    int iy = (int)floorf((v + 1.0f) * hg);
+    ix = (int)floorf((u + 1.0f) * hg);
+    iy = (int)floorf((v + 1.0f) * hg);
     ix = ix < 0 ? 0 : (ix > G - 1 ? G - 1 : ix);
     iy = iy < 0 ? 0 : (iy > G - 1 ? G - 1 : iy);
-    return iy * G + ix;
+    return true;
 }
 
-// One wave walks one circle at a time, 64 consecutive samples per step.
-// Consecutive samples mostly share a cell, so each run of equal cells along
-// the wave is added by its first lane with one atomic.
-__device__ __forceinline__ void sample_circles(const float* __restrict__ P, const float* __restrict__ Q, int64_t N,
-                                               const Inst& I, int64_t l0, int64_t l1, const float* cs,
-                                               const float* sn, uint32_t* __restrict__ grid) {
+// Per-circle record of the band pass (kSampleRec words): the frame (alpha1,
+// alpha2), the window of sample indices [js, js + L) (mod J) that holds every
+// southern sample, a row margin M, and the rows floor((v + 1) G/2) of the 64
+// checkpoints js + (k L)/63, k = 0..63, as int16.  Every sample between
+// checkpoints k and k+1 has its row within M of theirs: the projected arc
+// between them is shorter than l = dtheta (L/63 + 1) * 1.02 (the projection
+// scales lengths by 1/(1 - s_z) <= 1.02 in the window) and, as an arc of a
+// circle of radius at least 1 (or a line), leaves their chord by at most
+// l^2/8.
+__device__ __forceinline__ float sample_row_coord(const float* a1, const float* a2, float c, float sn, float hg) {
+    const float s1 = (a1[1] * c) + (a2[1] * sn);
+    const float s2 = (a1[2] * c) + (a2[2] * sn);
+    return ((s1 / (1.0f - s2)) + 1.0f) * hg;
+}
+
+__global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ P, const float* __restrict__ Q,
+                                                      int64_t N, const Inst* __restrict__ insts,
+                                                      const int4* __restrict__ items, uint32_t* __restrict__ recs) {
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int J = I.J, G = I.G;
     const float hg = 0.5f * (float)G;
-    for (int64_t li = l0 + wave; li < l1; li += nw) {
+    const float dth = 6.28318531f / (float)J;
+    for (int64_t li = wi.y + wave; li < wi.z; li += nw) {
         const int64_t i = I.off + li;
+        uint32_t* rec = recs + (I.ssetup_off + li) * kSampleRec;
         const float p[3] = {P[i], P[N + i], P[2 * N + i]};
         const float q[3] = {Q[i], Q[N + i], Q[2 * N + i]};
-        float a1[3], a2[3];
-        if (!sample_frame(p, q, a1, a2)) continue;   // same inputs on every lane: uniform
-        for (int j0 = 0; j0 < J; j0 += 64) {
-            const int j = j0 + lane;
-            int cell = -1;
-            if (j < J) cell = sample_cell(a1, a2, cs[j], sn[j], G, hg);
-            const int prev = __shfl_up(cell, 1);
-            const bool head = lane == 0 || prev != cell;
-            const unsigned long long heads = __ballot(head);
-            if (head && cell >= 0) {
-                const unsigned long long later = lane == 63 ? 0ull : (heads >> (lane + 1));
-                const uint32_t len = later ? (uint32_t)__builtin_ctzll(later) + 1u : (uint32_t)(64 - lane);
-                atomicAdd(&grid[cell], len);
+        float a1[3] = {0.0f, 0.0f, 0.0f}, a2[3] = {0.0f, 0.0f, 0.0f};
+        int js = 0, L = 0, M = 0;
+        const bool ok = sample_frame(p, q, a1, a2);   // uniform
+        if (ok) {
+            // s_z = a1z cos t + a2z sin t is at most 0 on the half circle
+            // centred on t = atan2(a2z, a1z) + pi; within 0.01 of the equator
+            // plane every sample may be southern
+            const float rz2 = (a1[2] * a1[2]) + (a2[2] * a2[2]);
+            float scale = 1.0102f;   // bound on 1/(1 - s_z) over the window
+            bool all_rows = false;
+            if (rz2 < 1e-4f) {
+                js = 0;
+                L = J;
+            } else {
+                const float t0 = atan2f(a2[2], a1[2]) + 1.57079633f;   // start of the southern half
+                const int j0 = (int)ceilf((t0 + 3.14159265f) / dth) - 4;
+                L = (int)ceilf(3.14159265f / dth) + 9;
+                js = ((j0 % J) + J) % J;
+                // the window reaches 4.5 sample steps past the southern half
+                const float sm = sqrtf(rz2) * sinf(fminf(4.5f * dth, 1.57079633f));
+                if (L >= J || sm > 0.5f) {   // few samples: walk the whole circle in every band
+                    js = 0;
+                    L = J;
+                    all_rows = true;
+                } else {
+                    scale = 1.0f / (1.0f - sm);
+                }
             }
+            const float l = dth * ((float)L / 63.0f + 1.0f) * scale * 1.01f;
+            M = all_rows ? 2 * G : (int)ceilf(l * l * 0.125f * hg + 0.05f) + 1;
+            M = M < 2 * G ? M : 2 * G;
         }
+        if (lane < 8) {
+            const float f = lane == 0 ? a1[0] : lane == 1 ? a1[1] : lane == 2 ? a1[2]
+                          : lane == 3 ? a2[0] : lane == 4 ? a2[1] : a2[2];
+            rec[lane] = lane < 6 ? __float_as_uint(f)
+                                 : (lane == 6 ? (uint32_t)js : ((uint32_t)L | ((uint32_t)M << 20)));
+        }
+        if (!ok) continue;
+        int c = js + (lane * L) / 63;
+        if (c >= J) c -= J;
+        float t = sample_row_coord(a1, a2, I.scs[c], I.ssn[c], hg);
+        t = fminf(fmaxf(t, -2.0f), (float)(G + 1));   // also maps NaN to -2
+        const int r = (int)floorf(t);
+        reinterpret_cast<int16_t*>(rec + 8)[lane] = (int16_t)r;
     }
 }
 
-__global__ __launch_bounds__(1024) void k_sample_vote(const float* __restrict__ P, const float* __restrict__ Q,
-                                                      int64_t N, const Inst* __restrict__ insts,
-                                                      const int4* __restrict__ items,
-                                                      uint32_t* __restrict__ grid_arena) {
+// Band pass: one work item = (instance, band of rows [r0, r1), circles
+// [c0, c1)).  A wave takes one circle at a time (its record loaded while the
+// previous circle is walked), finds the checkpoint intervals whose rows may
+// reach the band, and walks only their samples, 64 per step, with the exact
+// per-sample cell, counting them in the LDS tile.  The tile is then stored
+// whole to the item's slot of the partial arena (no global atomics).
+__global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ insts, const int4* __restrict__ items,
+                                                      const uint32_t* __restrict__ recs,
+                                                      uint32_t* __restrict__ part) {
     extern __shared__ __align__(16) uint32_t sm[];
     const int4 wi = items[blockIdx.x];
     const Inst& I = insts[wi.x];
-    uint32_t* grid = grid_arena + I.grid_off;
-    const int J = I.J;
-    if (J <= kSampleLdsMax) {
-        float* cs = reinterpret_cast<float*>(sm);
-        float* sn = cs + J;
-        for (int j = threadIdx.x; j < J; j += blockDim.x) {
-            cs[j] = I.scs[j];
-            sn[j] = I.ssn[j];
+    const int G = I.G, J = I.J, bw = I.sbw;
+    const int band = wi.y;
+    const int r0 = band * bw, r1 = r0 + bw;
+    const int cells = bw * G;
+    // LDS: the sample directions (when they fit), then the band tile
+    const bool lds_dirs = I.sdir_lds != 0;
+    float* ldir = reinterpret_cast<float*>(sm);
+    uint32_t* tile = sm + (lds_dirs ? 2 * J : 0);
+    for (int e = threadIdx.x; e < cells; e += blockDim.x) tile[e] = 0u;
+    if (lds_dirs)
+        for (int e = threadIdx.x; e < J; e += blockDim.x) {
+            ldir[e] = I.scs[e];
+            ldir[J + e] = I.ssn[e];
         }
-        __syncthreads();
-        sample_circles(P, Q, N, I, wi.y, wi.z, cs, sn, grid);
-    } else {
-        sample_circles(P, Q, N, I, wi.y, wi.z, I.scs, I.ssn, grid);
+    __syncthreads();
+    const float* cs = lds_dirs ? ldir : I.scs;
+    const float* sn = lds_dirs ? ldir + J : I.ssn;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const float hg = 0.5f * (float)G;
+    // the next circle's record is loaded while the current one is walked
+    int64_t li = wi.z + wave;
+    uint32_t hn = 0u;
+    int rn_row = 0;
+    if (li < wi.w) {
+        const uint32_t* rec = recs + (I.ssetup_off + li) * kSampleRec;
+        hn = rec[lane < 8 ? lane : 7];
+        rn_row = reinterpret_cast<const int16_t*>(rec + 8)[lane];
+    }
+    for (; li < wi.w; li += nw) {
+        const uint32_t hw = hn;
+        const int rk = rn_row;
+        if (li + nw < wi.w) {
+            const uint32_t* rec = recs + (I.ssetup_off + li + nw) * kSampleRec;
+            hn = rec[lane < 8 ? lane : 7];
+            rn_row = reinterpret_cast<const int16_t*>(rec + 8)[lane];
+        }
+        const uint32_t lw = __shfl(hw, 7);
+        const int L = (int)(lw & 0xFFFFFu), M = (int)(lw >> 20);
+        if (L == 0) continue;   // uniform
+        const float a1[3] = {__uint_as_float(__shfl(hw, 0)), __uint_as_float(__shfl(hw, 1)),
+                             __uint_as_float(__shfl(hw, 2))};
+        const float a2[3] = {__uint_as_float(__shfl(hw, 3)), __uint_as_float(__shfl(hw, 4)),
+                             __uint_as_float(__shfl(hw, 5))};
+        const int js = (int)__shfl(hw, 6);
+        const int rn = __shfl_down(rk, 1);
+        const int lo = (rk < rn ? rk : rn) - M, hi = (rk > rn ? rk : rn) + M;
+        const int ck = (lane * L) / 63, cn = ((lane + 1) * L) / 63;
+        const bool hit = lane < 63 && cn > ck && hi >= r0 && lo < r1;
+        unsigned long long mask = __ballot(hit);
+        while (mask) {
+            const int k = __builtin_ctzll(mask);
+            const int e = k + __builtin_ctzll(~(mask >> k));   // bit 63 is never set
+            mask &= ~(((1ull << (e - k)) - 1ull) << k);
+            const int jb = js + (k * L) / 63, je = js + (e * L) / 63;
+            for (int j0 = jb; j0 < je; j0 += 64) {
+                const int j = j0 + lane;
+                int cell = -1;
+                if (j < je) {
+                    const int idx = j >= J ? j - J : j;
+                    int ix, iy;
+                    if (sample_cell(a1, a2, cs[idx], sn[idx], G, hg, ix, iy) && iy >= r0 && iy < r1)
+                        cell = (iy - r0) * G + ix;
+                }
+                // LDS atomics: lanes of a run of equal cells serialise on one
+                // address, which costs less here than merging the run first
+                if (cell >= 0) atomicAdd(&tile[cell], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    const int chunk = wi.z / I.schunk;
+    uint32_t* dst = part + I.spart_off + ((int64_t)chunk * I.snb + band) * cells;
+    for (int e = threadIdx.x; e < cells; e += blockDim.x) dst[e] = tile[e];
+}
+
+// grid cell = sum over the instance's circle chunks of its band slot.
+__global__ __launch_bounds__(256) void k_sample_reduce(const Inst* __restrict__ insts, const int4* __restrict__ items,
+                                                       const uint32_t* __restrict__ part,
+                                                       uint32_t* __restrict__ grid_arena) {
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
+    if (I.rule != 1 || I.n == 0) return;
+    const int G = I.G, bw = I.sbw, cells = bw * G;
+    const int nch = (I.n + I.schunk - 1) / I.schunk;
+    uint32_t* grid = grid_arena + I.grid_off;
+    // blockIdx.y splits the item into runs of blockDim.x cells (one cell per thread)
+    for (int c = wi.y + (int)(blockIdx.y * blockDim.x + threadIdx.x); c < wi.z; c += gridDim.y * blockDim.x) {
+        const int band = (c / G) / bw;
+        const int within = c - band * cells;
+        const uint32_t* src = part + I.spart_off + (int64_t)band * cells + within;
+        uint32_t acc = 0u;
+        for (int h = 0; h < nch; ++h) acc += src[(int64_t)h * I.snb * cells];
+        grid[c] = acc;
     }
 }
 
@@ -1483,10 +1616,22 @@ void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, 
     hipLaunchKernelGGL(k_fine_peak, dim3((unsigned)ninst), dim3(1024), 0, s, fine_arena, insts, st, slot);
 }
 
-void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* items, int nitems,
-                        uint32_t* grid_arena, size_t lds_bytes, hipStream_t s) {
-    if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_sample_vote, dim3((unsigned)nitems), dim3(1024), lds_bytes, s, P, Q, N, insts, items,
+void sample_layout(int G, int J, int& bw, int& dirs_in_lds, size_t& lds_bytes) {
+    // the tile keeps its full size (fewer bands: less work per circle); the
+    // directions join it in LDS only where they fit beside it
+    const int cells = G * G < kSampleTile ? G * G : kSampleTile;
+    dirs_in_lds = (size_t)cells * 4 + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
+    bw = cells / G;
+    lds_bytes = (size_t)cells * 4 + (dirs_in_lds ? (size_t)J * 8 : 0);
+}
+
+void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* setup_items,
+                        int nsetup, const int4* band_items, int nband, const int4* cell_items, int ncell,
+                        uint32_t* recs, uint32_t* part, uint32_t* grid_arena, size_t lds_bytes, hipStream_t s) {
+    if (nband <= 0) return;
+    hipLaunchKernelGGL(k_sample_setup, dim3((unsigned)nsetup), dim3(256), 0, s, P, Q, N, insts, setup_items, recs);
+    hipLaunchKernelGGL(k_sample_vote, dim3((unsigned)nband), dim3(1024), lds_bytes, s, insts, band_items, recs, part);
+    hipLaunchKernelGGL(k_sample_reduce, dim3((unsigned)ncell, 32), dim3(256), 0, s, insts, cell_items, part,
                        grid_arena);
 }
 

@@ -71,6 +71,7 @@ struct Workspace {
     DevBuf out;                     // results, peak states, flag and counter (OutLayout)
     DevBuf icount;                  // partial inlier counters (kCountSlots per result slot)
     DevBuf lsum;                    // least-squares sums per correspondence item (kLsWords doubles)
+    DevBuf srec, spart;             // sampling rule: circle records, partial band tiles
     DevBuf plan;                    // instance table + work items
     DevBuf P, Q, masks;             // staging for host-pointer entry points
     HostBuf h_plan, h_out;          // pinned mirrors
@@ -82,7 +83,8 @@ struct Workspace {
 // A batch laid out for the kernels.
 struct Plan {
     std::vector<Inst> insts;
-    std::vector<int4> vote_items, cell_items, corr_items, list_items, sample_items;
+    std::vector<int4> vote_items, cell_items, corr_items, list_items;
+    std::vector<int4> sample_setup_items, sample_items;   // sampling rule: circle records, band items
     int64_t N = 0;
     size_t grid_cells = 0, fine_cells = 0, hist_cells = 0;
     size_t fhist_cells = 0;    // fine-angle windows, after the histograms in the same arena
@@ -90,7 +92,9 @@ struct Plan {
     int max_npk = 0, maxM = 0;
     size_t hist_lds = 0;
     size_t fhist_lds = 0;      // 0: no instance refines its angle
-    size_t sample_lds = 0;     // LDS of the sampling vote (sample directions staged per block)
+    size_t sample_lds = 0;     // LDS of the sampling band pass (0: no instance uses the sampling rule)
+    size_t sample_recs = 0;    // circle records of the sampling rule
+    size_t sample_part = 0;    // u32 cells of its partial tiles
 };
 
 // Work split of the coarse vote for one (G, n bucket): LDS tile cells and

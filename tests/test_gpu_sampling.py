@@ -59,8 +59,11 @@ def assert_ls(orc, r, P, Q, mask):
     (64, 100, 700, 1),        # J not a multiple of the wave width: ragged last step
     (128, 1024, 1500, 2),     # the default J = 8 G
     (256, 2048, 1200, 3),
-    (64, 20000, 300, 4),      # J above the LDS table limit: directions read from HBM
+    (64, 20000, 300, 4),      # the whole 64 x 64 grid in one band tile
     (512, 4, 2000, 5),        # four samples per circle
+    (512, 37, 1000, 6),       # few samples: every band walks the whole circle
+    (2048, 16384, 200, 7),    # band tiles of 16 rows
+    (4096, 65536, 40, 8),     # the largest grid and sample count
 ])
 def test_sample_grid_bit_exact(aor, orc, G, J, n, seed):
     inst = synth.make_instance(n, 5100 + seed)
