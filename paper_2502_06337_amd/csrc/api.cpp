@@ -37,6 +37,14 @@ static aoresp_status hip_fail(hipError_t e, const char* what, int line) {
 
 static bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
+int64_t sample_chunk(int G, int64_t n) {
+    // at most 32 chunks, and at most 2^27 partial cells per instance
+    int64_t maxch = ((int64_t)1 << 27) / ((int64_t)G * G);
+    maxch = maxch < 1 ? 1 : (maxch > 32 ? 32 : maxch);
+    int64_t ch = (n + maxch - 1) / maxch;
+    return ch < 2048 ? 2048 : (ch + 15) / 16 * 16;
+}
+
 aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams& rp) {
     aoresp_params p{};
     if (prm) p = *prm;
@@ -282,11 +290,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
             size_t slds = 0;
             sample_layout(rp.G, rp.J, I.sbw, I.sdir_lds, slds);
             I.snb = rp.G / I.sbw;
-            // circles per band item: at most 32 chunks, and at most 2^27 partial cells per instance
-            int64_t maxch = ((int64_t)1 << 27) / ((int64_t)rp.G * rp.G);
-            maxch = maxch < 1 ? 1 : (maxch > 32 ? 32 : maxch);
-            int64_t ch = (n + maxch - 1) / maxch;
-            ch = ch < 2048 ? 2048 : (ch + 15) / 16 * 16;
+            const int64_t ch = sample_chunk(rp.G, n);
             I.schunk = (int32_t)ch;
             I.ssetup_off = (int64_t)plan.sample_recs;
             plan.sample_recs += (size_t)n;

@@ -7,6 +7,10 @@
 //                    and row pass over horizontal LDS bands, persistent
 //                    work-groups pulling (instance, band, chunk) items
 //                    (Sec. IV-A, Fig. 3(c))
+//   k_sample_setup / k_sample_vote / k_sample_reduce
+//                    alternative coarse accumulator by the literal sampling
+//                    loop of Algorithm 1: per-circle records, LDS band tiles,
+//                    sum of the per-chunk partial tiles
 //   k_peak           argmax (ties to the lowest index), suppression of earlier
 //                    peaks for multi-model estimation (Sec. IV-D)
 //   k_fine_vote      refinement accumulator around each peak

@@ -103,3 +103,24 @@ def test_destroy_drains_queue(aor):
     st, _, _ = srv.poll(ids[0], timeout_us=-1)
     assert st == aor.OK
     srv.close()   # the rest are drained before the loop exits
+
+
+def test_served_options_equal_solo(aor):
+    """Requests that mix the sampling rule, the angle gate and fine angle
+    bins share batches; each served result equals its solo solve."""
+    rng = np.random.default_rng(11)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(500), np.log(20000), 12))]
+    probs = [synth.make_instance(n, 9500 + t, outlier_rate=0.85) for t, n in enumerate(sizes)]
+    opts = [dict(vote_rule=t % 2, circle_samples=(0, 700, 2048)[t % 3], angle_gate=(t // 2) % 2,
+                 angle_refine=(0, 8, 1)[t % 3]) for t in range(len(probs))]
+    prms = [aor.SolveParams(angle_bins=360, **o) for o in opts]
+    srv = aor.Server(hbm_budget_bytes=256 << 20, max_slots=6)
+    ids = [srv.submit(p.P, p.Q, prm) for p, prm in zip(probs, prms)]
+    served = [srv.poll(rid, timeout_us=-1) for rid in ids]
+    srv.close()
+    for t, (st, res, mask) in enumerate(served):
+        r1, m1, st1 = aor.est_rotation(probs[t].P, probs[t].Q, prms[t])
+        assert st == st1
+        assert same(res, r1), (t, opts[t])
+        assert res["angle_fine_bin"] == r1["angle_fine_bin"] and res["angle_fine_votes"] == r1["angle_fine_votes"]
+        assert np.array_equal(mask, m1)
