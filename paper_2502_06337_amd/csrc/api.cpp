@@ -37,14 +37,6 @@ static aoresp_status hip_fail(hipError_t e, const char* what, int line) {
 
 static bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
-int64_t sample_chunk(int G, int64_t n) {
-    // at most 32 chunks, and at most 2^27 partial cells per instance
-    int64_t maxch = ((int64_t)1 << 27) / ((int64_t)G * G);
-    maxch = maxch < 1 ? 1 : (maxch > 32 ? 32 : maxch);
-    int64_t ch = (n + maxch - 1) / maxch;
-    return ch < 2048 ? 2048 : (ch + 15) / 16 * 16;
-}
-
 aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams& rp) {
     aoresp_params p{};
     if (prm) p = *prm;
@@ -287,16 +279,17 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
             if (!sd) return AORESP_ENOMEM;
             I.scs = sd->tc;
             I.ssn = sd->ts;
-            size_t slds = 0;
-            sample_layout(rp.G, rp.J, I.sbw, I.sdir_lds, slds);
+            const SampleLayout sl = sample_plan(rp.G, rp.J, n);
+            I.sbw = sl.bw;
+            I.shalf = sl.half;
+            I.sdir_lds = sl.dirs_lds;
             I.snb = rp.G / I.sbw;
-            const int64_t ch = sample_chunk(rp.G, n);
-            I.schunk = (int32_t)ch;
+            I.schunk = (int32_t)sl.chunk;
             I.ssetup_off = (int64_t)plan.sample_recs;
             plan.sample_recs += (size_t)n;
             I.spart_off = (int64_t)plan.sample_part;
-            plan.sample_part += (size_t)((n + ch - 1) / ch) * rp.G * rp.G;
-            if (slds > plan.sample_lds) plan.sample_lds = slds;
+            plan.sample_part += (size_t)sl.part_words;
+            if (sl.lds_bytes > plan.sample_lds) plan.sample_lds = sl.lds_bytes;
         }
         // coarse-vote work split: forced (tuner candidate), tuned for (G, n), or default
         const Tuning tu = force ? *force : tuning_for(ctx, rp.G, n);

@@ -78,9 +78,10 @@ struct Inst {
     const float* ssn;
     int32_t sbw, snb;     // rule 1: rows per band tile, bands
     int32_t sdir_lds;     // rule 1: sample directions staged in LDS
+    int32_t shalf;        // rule 1: 16-bit band counters (partial tiles hold two per word)
     int32_t schunk;       // rule 1: circles per band item
     int64_t ssetup_off;   // rule 1: first circle record
-    int64_t spart_off;    // rule 1: u32 offset of its partial tiles (chunks x bands x sbw*G)
+    int64_t spart_off;    // rule 1: u32 offset of its partial tiles (chunks x bands x tile words)
 };
 
 struct FineWin {
@@ -148,10 +149,17 @@ void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, 
 constexpr int kSampleTile = 32768;    // u32 counters per band tile (128 KiB of LDS), or the whole grid if smaller
 constexpr int kSampleRec = 40;        // u32 words per circle record
 constexpr int kSampleSetupChunk = 1024;
-// Band tile rows (a power of two), whether the sample directions are staged
-// in LDS beside the tile (when both fit in 160 KiB), and the LDS bytes of a
-// block.
-void sample_layout(int G, int J, int& bw, int& dirs_in_lds, size_t& lds_bytes);
+// Layout of the sampling band pass for an instance of n circles: band tile
+// rows (a power of two), 16-bit counters (two per word) where the per-item
+// count bound allows it, else 32-bit, circles per band item, partial arena
+// words, whether the sample directions are staged in LDS beside the tile
+// (when both fit in 160 KiB), and the LDS bytes of a block.
+struct SampleLayout {
+    int bw = 0, half = 0, dirs_lds = 0;
+    int64_t chunk = 0, part_words = 0;
+    size_t lds_bytes = 0;
+};
+SampleLayout sample_plan(int G, int J, int64_t n);
 void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* setup_items,
                         int nsetup, const int4* band_items, int nband, const int4* cell_items, int ncell,
                         uint32_t* recs, uint32_t* part, uint32_t* grid_arena, size_t lds_bytes, hipStream_t s);

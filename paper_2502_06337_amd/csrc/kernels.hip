@@ -30,6 +30,8 @@
 // work per vote and LDS atomics, the rest by HBM streaming.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <cmath>
 #include <stdint.h>
 
 #include "geometry.h"
@@ -935,11 +937,13 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
     const int band = wi.y;
     const int r0 = band * bw, r1 = r0 + bw;
     const int cells = bw * G;
+    const bool half = I.shalf != 0;   // 16-bit counters: cells 2m and 2m + 1 share word m
+    const int words = half ? cells >> 1 : cells;
     // LDS: the sample directions (when they fit), then the band tile
     const bool lds_dirs = I.sdir_lds != 0;
     float* ldir = reinterpret_cast<float*>(sm);
     uint32_t* tile = sm + (lds_dirs ? 2 * J : 0);
-    for (int e = threadIdx.x; e < cells; e += blockDim.x) tile[e] = 0u;
+    for (int e = threadIdx.x; e < words; e += blockDim.x) tile[e] = 0u;
     if (lds_dirs)
         for (int e = threadIdx.x; e < J; e += blockDim.x) {
             ldir[e] = I.scs[e];
@@ -997,17 +1001,21 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
                 }
                 // LDS atomics: lanes of a run of equal cells serialise on one
                 // address, which costs less here than merging the run first
-                if (cell >= 0) atomicAdd(&tile[cell], 1u);
+                if (cell >= 0) {
+                    if (half) atomicAdd(&tile[cell >> 1], 1u << ((cell & 1) << 4));
+                    else atomicAdd(&tile[cell], 1u);
+                }
             }
         }
     }
     __syncthreads();
     const int chunk = wi.z / I.schunk;
-    uint32_t* dst = part + I.spart_off + ((int64_t)chunk * I.snb + band) * cells;
-    for (int e = threadIdx.x; e < cells; e += blockDim.x) dst[e] = tile[e];
+    uint32_t* dst = part + I.spart_off + ((int64_t)chunk * I.snb + band) * words;
+    for (int e = threadIdx.x; e < words; e += blockDim.x) dst[e] = tile[e];
 }
 
-// grid cell = sum over the instance's circle chunks of its band slot.
+// grid cell = sum over the instance's circle chunks of its band slot.  With
+// 16-bit counters a thread sums one word, i.e. the two cells 2m and 2m + 1.
 __global__ __launch_bounds__(256) void k_sample_reduce(const Inst* __restrict__ insts, const int4* __restrict__ items,
                                                        const uint32_t* __restrict__ part,
                                                        uint32_t* __restrict__ grid_arena) {
@@ -1015,16 +1023,31 @@ __global__ __launch_bounds__(256) void k_sample_reduce(const Inst* __restrict__ 
     const Inst& I = insts[wi.x];
     if (I.rule != 1 || I.n == 0) return;
     const int G = I.G, bw = I.sbw, cells = bw * G;
+    const bool half = I.shalf != 0;
+    const int words = half ? cells >> 1 : cells;
     const int nch = (I.n + I.schunk - 1) / I.schunk;
+    const int64_t stride = (int64_t)I.snb * words;
     uint32_t* grid = grid_arena + I.grid_off;
-    // blockIdx.y splits the item into runs of blockDim.x cells (one cell per thread)
-    for (int c = wi.y + (int)(blockIdx.y * blockDim.x + threadIdx.x); c < wi.z; c += gridDim.y * blockDim.x) {
+    const int step = half ? 2 : 1;   // cells per thread (item bounds are even)
+    for (int c = wi.y + step * (int)(blockIdx.y * blockDim.x + threadIdx.x); c < wi.z;
+         c += step * (int)(gridDim.y * blockDim.x)) {
         const int band = (c / G) / bw;
         const int within = c - band * cells;
-        const uint32_t* src = part + I.spart_off + (int64_t)band * cells + within;
-        uint32_t acc = 0u;
-        for (int h = 0; h < nch; ++h) acc += src[(int64_t)h * I.snb * cells];
-        grid[c] = acc;
+        const uint32_t* src = part + I.spart_off + (int64_t)band * words + (half ? within >> 1 : within);
+        if (half) {
+            uint32_t lo = 0u, hi = 0u;
+            for (int h = 0; h < nch; ++h) {
+                const uint32_t v = src[h * stride];
+                lo += v & 0xFFFFu;
+                hi += v >> 16;
+            }
+            grid[c] = lo;
+            grid[c + 1] = hi;
+        } else {
+            uint32_t acc = 0u;
+            for (int h = 0; h < nch; ++h) acc += src[h * stride];
+            grid[c] = acc;
+        }
     }
 }
 
@@ -1620,13 +1643,49 @@ void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, 
     hipLaunchKernelGGL(k_fine_peak, dim3((unsigned)ninst), dim3(1024), 0, s, fine_arena, insts, st, slot);
 }
 
-void sample_layout(int G, int J, int& bw, int& dirs_in_lds, size_t& lds_bytes) {
-    // the tile keeps its full size (fewer bands: less work per circle); the
-    // directions join it in LDS only where they fit beside it
-    const int cells = G * G < kSampleTile ? G * G : kSampleTile;
-    dirs_in_lds = (size_t)cells * 4 + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
-    bw = cells / G;
-    lds_bytes = (size_t)cells * 4 + (dirs_in_lds ? (size_t)J * 8 : 0);
+SampleLayout sample_plan(int G, int J, int64_t n) {
+    SampleLayout L;
+    const int64_t GG = (int64_t)G * G;
+    const auto round16 = [](int64_t x) { return (x + 15) / 16 * 16; };
+    // 16-bit counters when one item cannot carry a counter: the samples one
+    // circle puts in one cell lie on an arc inside the cell, shorter than
+    // 1.01 times its diagonal sqrt(2) h (a circle of radius >= 1 through a cell
+    // of side h <= 1/32), and consecutive southern samples are at least
+    // 0.45 dtheta apart in the plane (the projection shrinks lengths by at most
+    // 2, and the chord of such a short arc is within 1% of it), so at most
+    // 1 + sqrt(2) 1.01 h / (0.45 dtheta) = 1 + 1.01 J / G samples; an item of
+    // at most 65535 / that many circles cannot overflow.
+    const int64_t spc = 1 + (int64_t)std::ceil(1.01 * (double)J / (double)G);
+    const int64_t cap16 = (65535 / spc) / 16 * 16;
+    if (J >= 64 && cap16 >= 1024) {
+        int64_t ch = round16((n + 31) / 32);
+        ch = ch < 2048 ? 2048 : ch;
+        ch = ch < cap16 ? ch : cap16;
+        const int64_t nch = n > 0 ? (n + ch - 1) / ch : 0;
+        const int64_t cells = GG < 65536 ? GG : 65536;
+        if (nch * (GG / 2) <= ((int64_t)1 << 27)) {
+            L.half = 1;
+            L.bw = (int)(cells / G);
+            L.chunk = ch;
+            L.part_words = nch * (GG / 2);
+            L.dirs_lds = (size_t)cells * 2 + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
+            L.lds_bytes = (size_t)cells * 2 + (L.dirs_lds ? (size_t)J * 8 : 0);
+            return L;
+        }
+    }
+    // 32-bit counters: at most 32 chunks, and at most 2^27 partial words
+    int64_t maxch = ((int64_t)1 << 27) / GG;
+    maxch = maxch < 1 ? 1 : (maxch > 32 ? 32 : maxch);
+    int64_t ch = (n + maxch - 1) / maxch;
+    ch = ch < 2048 ? 2048 : round16(ch);
+    const int64_t cells = GG < kSampleTile ? GG : kSampleTile;
+    L.half = 0;
+    L.bw = (int)(cells / G);
+    L.chunk = ch;
+    L.part_words = (n > 0 ? (n + ch - 1) / ch : 0) * GG;
+    L.dirs_lds = (size_t)cells * 4 + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
+    L.lds_bytes = (size_t)cells * 4 + (L.dirs_lds ? (size_t)J * 8 : 0);
+    return L;
 }
 
 void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* insts, const int4* setup_items,

@@ -21,10 +21,6 @@ struct ResolvedParams {
 
 aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams& rp);
 
-// Sampling rule: circles per band item of an instance of n circles on a G x G
-// grid (the instance's partial arena holds ceil(n / chunk) tiles of G*G u32).
-int64_t sample_chunk(int G, int64_t n);
-
 // Device buffers of one angle-table size B.
 struct AngleTables {
     float* tc = nullptr;   // boundary directions cos(phi_k), phi_k = -pi + k*2pi/B

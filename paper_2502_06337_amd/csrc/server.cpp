@@ -105,10 +105,7 @@ struct Pipeline {
 size_t request_bytes(size_t n, const ResolvedParams& rp) {
     size_t b = n * (24 + 64 + 1) + (size_t)rp.G * rp.G * 4 + (size_t)rp.M * rp.M * 4 + (size_t)rp.B * 4 + 4096;
     if (rp.F > 1) b += (size_t)rp.F * 3 * 4;
-    if (rp.rule == 1 && n > 0) {
-        const int64_t ch = sample_chunk(rp.G, (int64_t)n);
-        b += n * kSampleRec * 4 + (size_t)((n + ch - 1) / ch) * rp.G * rp.G * 4;
-    }
+    if (rp.rule == 1 && n > 0) b += n * kSampleRec * 4 + (size_t)sample_plan(rp.G, rp.J, (int64_t)n).part_words * 4;
     return b;
 }
 

@@ -159,3 +159,16 @@ def test_sample_rule_at_full_grid_and_samples(aor, orc):
     ref = orc.sample_grid(inst.P, inst.Q, 1024, 8192)
     assert np.array_equal(g, ref)
     assert out["result"]["peak_cell"] == int(np.argmax(ref.ravel()))
+
+
+@pytest.mark.parametrize("d", [(0.3, -0.2, 0.9), (0.0, 0.0, 1.0)])
+def test_sample_counts_in_packed_tiles(aor, orc, d):
+    """2.1e5 copies of one circle (items of 6544 circles, the most the 16-bit
+    band counters allow at J = 8 G): every cell equals the copy count times the
+    oracle's count for one circle."""
+    n, G, J = 210_000, 128, 1024
+    Q = np.tile(np.asarray(d, np.float32)[:, None], (1, n))
+    P = np.zeros_like(Q)
+    g, _ = gpu_sample_grid(aor, P, Q, G, J)
+    one = orc.sample_grid(P[:, :1], Q[:, :1], G, J).astype(np.int64)
+    assert np.array_equal(g.astype(np.int64), one * n)
