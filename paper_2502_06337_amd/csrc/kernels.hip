@@ -990,13 +990,31 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
             const int e = k + __builtin_ctzll(~(mask >> k));   // bit 63 is never set
             mask &= ~(((1ull << (e - k)) - 1ull) << k);
             const int jb = js + (k * L) / 63, je = js + (e * L) / 63;
+            // the directions of the next step are loaded while this one is evaluated
+            float cnx = 0.0f, snx = 0.0f;
+            {
+                const int j = jb + lane;
+                const int idx = j >= J ? j - J : j;
+                if (j < je) {
+                    cnx = cs[idx];
+                    snx = sn[idx];
+                }
+            }
             for (int j0 = jb; j0 < je; j0 += 64) {
                 const int j = j0 + lane;
+                const float c_cur = cnx, s_cur = snx;
+                {
+                    const int jn = j + 64;
+                    const int idn = jn >= J ? jn - J : jn;
+                    if (jn < je) {
+                        cnx = cs[idn];
+                        snx = sn[idn];
+                    }
+                }
                 int cell = -1;
                 if (j < je) {
-                    const int idx = j >= J ? j - J : j;
                     int ix, iy;
-                    if (sample_cell(a1, a2, cs[idx], sn[idx], G, hg, ix, iy) && iy >= r0 && iy < r1)
+                    if (sample_cell(a1, a2, c_cur, s_cur, G, hg, ix, iy) && iy >= r0 && iy < r1)
                         cell = (iy - r0) * G + ix;
                 }
                 // LDS atomics: lanes of a run of equal cells serialise on one
