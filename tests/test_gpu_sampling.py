@@ -172,3 +172,26 @@ def test_sample_counts_in_packed_tiles(aor, orc, d):
     g, _ = gpu_sample_grid(aor, P, Q, G, J)
     one = orc.sample_grid(P[:, :1], Q[:, :1], G, J).astype(np.int64)
     assert np.array_equal(g.astype(np.int64), one * n)
+
+
+def test_graph_replays_with_rules_and_angle_options(aor):
+    """Captured batch graphs with the sampling rule and the angle options,
+    replayed with the same and with changed compositions, eager solves and
+    synchronisations in between: every launch equals the one-at-a-time
+    results."""
+    comps = [[1500, 900, 2500], [1500, 900, 2500], [700, 3000, 1200, 400], [1500, 900, 2500]]
+    for rep, sizes in enumerate(comps):
+        insts = [synth.make_instance(n, 5600 + 13 * t, outlier_rate=0.85) for t, n in enumerate(sizes)]
+        P = np.concatenate([i.P for i in insts], axis=1)
+        Q = np.concatenate([i.Q for i in insts], axis=1)
+        off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+        prms = [aor.SolveParams(grid=128, angle_bins=360, vote_rule=(t + rep) % 2, circle_samples=512,
+                                angle_gate=t % 2, angle_refine=(4 if t % 3 else 0)) for t in range(len(sizes))]
+        outs, mask, _ = aor.est_rotation_batch(dev(P), dev(Q), off, prms)
+        mask = mask.cpu().numpy()
+        torch.cuda.synchronize()
+        for t in range(len(sizes)):
+            r1, m1, _ = aor.est_rotation(insts[t].P, insts[t].Q, prms[t])
+            assert_result_equal(outs[t], r1)
+            assert outs[t]["angle_fine_bin"] == r1["angle_fine_bin"]
+            assert np.array_equal(mask[off[t]:off[t + 1]], m1), (rep, t)
