@@ -195,3 +195,18 @@ def test_graph_replays_with_rules_and_angle_options(aor):
             assert_result_equal(outs[t], r1)
             assert outs[t]["angle_fine_bin"] == r1["angle_fine_bin"]
             assert np.array_equal(mask[off[t]:off[t + 1]], m1), (rep, t)
+
+
+def test_sample_rule_full_size_additivity(aor):
+    """The benchmark's launch (n = 1e6, G = 1024, J = 8192): the grid of all
+    circles equals the sum of the grids of two unequal parts, whose chunks,
+    band items and partial arenas differ from the full launch's, and every
+    circle casts about J/2 votes."""
+    inst = synth.make_instance(1_000_000, 2000)
+    g_all, _ = gpu_sample_grid(aor, inst.P, inst.Q, 1024, 0)
+    k = 377_777
+    g_a, _ = gpu_sample_grid(aor, inst.P[:, :k], inst.Q[:, :k], 1024, 0)
+    g_b, _ = gpu_sample_grid(aor, inst.P[:, k:], inst.Q[:, k:], 1024, 0)
+    assert np.array_equal(g_all.astype(np.int64), g_a.astype(np.int64) + g_b.astype(np.int64))
+    total = int(g_all.astype(np.int64).sum())
+    assert abs(total - 4096 * 1_000_000) <= 1_000_000
