@@ -168,3 +168,36 @@ def test_batch_mixed_angle_options(aor):
         assert np.array_equal(outs[t]["R"].view(np.uint32), r1["R"].view(np.uint32))
         assert np.array_equal(outs[t]["R_ls"].view(np.uint32), r1["R_ls"].view(np.uint32))
         assert np.array_equal(mask[off[t]:off[t + 1]], m1)
+
+
+def test_minimum_and_degenerate_inputs_with_options(aor, orc):
+    """n = 2 with every option on, against the oracle; all-degenerate input
+    (p = q) under either rule gives ENODATA and the identity."""
+    inst = synth.make_instance(2, 4600)
+    G, B, F = 64, 360, 10
+    prm = aor.SolveParams(grid=G, angle_bins=B, angle_gate=1, angle_refine=F, refine_grid=16)
+    r, m, st = aor.est_rotation(inst.P, inst.Q, prm)
+    base = orc.solve(inst.P, inst.Q, G=G, B=B, M=16)
+    if base["status"] == 0:
+        e, _ = expected(orc, inst.P, inst.Q, base, G, 1, B, F, 1)
+        assert_same(orc, r, e, inst.P, inst.Q, m)
+    P = np.random.default_rng(1).uniform(-1, 1, (3, 50)).astype(np.float32)
+    for rule in (0, 1):
+        prm = aor.SolveParams(grid=G, angle_bins=B, angle_gate=1, angle_refine=F, vote_rule=rule)
+        r, m, st = aor.est_rotation(P, P, prm)
+        assert st == aor.ENODATA
+        assert np.array_equal(r["R"], np.eye(3, dtype=np.float32))
+        assert r["angle_fine_bin"] == 0 and r["angle_fine_votes"] == 0
+
+
+def test_largest_refinement_with_fine_angle(aor, orc):
+    """G = 2048 with M = 128 (G M at its maximum 262144), B = 256, F = 256
+    (B F at its maximum), the gate on."""
+    inst = synth.make_instance(300, 4700, outlier_rate=0.8)
+    G, M, B, F = 2048, 128, 256, 256
+    prm = aor.SolveParams(grid=G, refine_grid=M, angle_bins=B, angle_gate=1, angle_refine=F)
+    r, m, st = aor.est_rotation(dev(inst.P), dev(inst.Q), prm)
+    assert st == 0
+    base = orc.solve(inst.P, inst.Q, G=G, B=B, M=M)
+    e, _ = expected(orc, inst.P, inst.Q, base, G, 1, B, F, 1)
+    assert_same(orc, r, e, inst.P, inst.Q, m.cpu().numpy())
