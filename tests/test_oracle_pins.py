@@ -743,3 +743,42 @@ def test_sample_rule_noise_free_peak(orc):
         u, v = e7(r)
         ix, iy = int((u + 1) * G / 2), int((v + 1) * G / 2)
         assert abs(pk % G - ix) <= 1 and abs(pk // G - iy) <= 1
+
+
+@pytest.mark.parametrize("G,J", [(64, 512), (128, 1024), (256, 4096), (64, 20000)])
+def test_sample_rule_samples_per_cell_bound(orc, G, J):
+    """One circle puts at most 1 + ceil(1.01 J / G) samples in one cell (its
+    samples in a cell lie on an arc shorter than the cell's diagonal, and
+    consecutive southern samples are at least half a step apart in the
+    plane): random circles, the equator, circles tangent to the rim and lines
+    through the centre."""
+    rng = np.random.default_rng(G + J)
+    D = rng.uniform(-1, 1, (3, 60))
+    D[:, 0] = (0, 0, 1)
+    D[:, 1] = (1, 0, 0)
+    D[:, 2] = (0.3, 0.4, 1e-3)
+    D[:, 3] = (1e-3, 0, 1)
+    D[:, 4] = (1, 1, 0)
+    D = D.astype(np.float32)
+    bound = 1 + math.ceil(1.01 * J / G)
+    worst = 0
+    for i in range(D.shape[1]):
+        g = orc.sample_grid(np.zeros((3, 1), np.float32), D[:, i:i + 1], G, J)
+        worst = max(worst, int(g.max()))
+    assert worst <= bound, (worst, bound)
+
+
+def test_angle_window_repeats_bins_when_B_below_3(orc):
+    """With B = 2 the window k-1, k, k+1 names a coarse bin twice: the
+    repeated fine bins carry the counts of the full B*F histogram, and the
+    fine bin is the first maximum in window order."""
+    inst = synth.make_instance(400, 67)
+    r_or = orc.solve(inst.P, inst.Q, G=64, B=2)
+    B, F = 2, 6
+    out = orc.angle_coarse_to_fine(inst.P, inst.Q, r_or["axis"], 64, r_or["peak_cell"], 1, B, F, gate=False)
+    full = orc.angle_hist(inst.P, inst.Q, r_or["axis"], B * F)
+    k = out["angle_bin"]
+    win = [((k + dc) % B) * F + j for dc in (-1, 0, 1) for j in range(F)]
+    assert np.array_equal(out["fine_hist"], full[win])
+    assert out["angle_fine_bin"] == win[int(np.argmax(full[win]))]
+    assert out["fine_hist"][:F].tolist() == out["fine_hist"][2 * F:].tolist()   # bins k-1 and k+1 coincide
