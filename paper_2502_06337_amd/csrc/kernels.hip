@@ -845,7 +845,8 @@ __device__ __forceinline__ bool sample_cell(const float* a1, const float* a2, fl
 
 // Per-circle record of the band pass (kSampleRec words): the frame (alpha1,
 // alpha2), the window of sample indices [js, js + L) (mod J) that holds every
-// southern sample, a row margin M, and the rows floor((v + 1) G/2) of the 64
+// southern sample, a row margin M (word 7 = L | M << 17), and the rows
+// floor((v + 1) G/2), clamped to [-2, G + 1], of the 64
 // checkpoints js + (k L)/63, k = 0..63, as int16.  Every sample between
 // checkpoints k and k+1 has its row within M of theirs: the projected arc
 // between them is shorter than l = dtheta (L/63 + 1) * 1.02 (the projection
@@ -902,14 +903,15 @@ __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ 
                 }
             }
             const float l = dth * ((float)L / 63.0f + 1.0f) * scale * 1.01f;
-            M = all_rows ? 2 * G : (int)ceilf(l * l * 0.125f * hg + 0.05f) + 1;
-            M = M < 2 * G ? M : 2 * G;
+            // stored rows lie in [-2, G + 1], so a margin of G + 4 reaches every row
+            M = all_rows ? G + 4 : (int)ceilf(fminf(l * l * 0.125f * hg + 0.05f, (float)G)) + 1;
+            M = M < G + 4 ? M : G + 4;
         }
         if (lane < 8) {
             const float f = lane == 0 ? a1[0] : lane == 1 ? a1[1] : lane == 2 ? a1[2]
                           : lane == 3 ? a2[0] : lane == 4 ? a2[1] : a2[2];
             rec[lane] = lane < 6 ? __float_as_uint(f)
-                                 : (lane == 6 ? (uint32_t)js : ((uint32_t)L | ((uint32_t)M << 20)));
+                                 : (lane == 6 ? (uint32_t)js : ((uint32_t)L | ((uint32_t)M << 17)));
         }
         if (!ok) continue;
         int c = js + (lane * L) / 63;
@@ -973,7 +975,7 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
             rn_row = reinterpret_cast<const int16_t*>(rec + 8)[lane];
         }
         const uint32_t lw = __shfl(hw, 7);
-        const int L = (int)(lw & 0xFFFFFu), M = (int)(lw >> 20);
+        const int L = (int)(lw & 0x1FFFFu), M = (int)(lw >> 17);   // L <= 65536, M <= G + 4 <= 4100
         if (L == 0) continue;   // uniform
         const float a1[3] = {__uint_as_float(__shfl(hw, 0)), __uint_as_float(__shfl(hw, 1)),
                              __uint_as_float(__shfl(hw, 2))};

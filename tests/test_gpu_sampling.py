@@ -64,6 +64,8 @@ def assert_ls(orc, r, P, Q, mask):
     (512, 37, 1000, 6),       # few samples: every band walks the whole circle
     (2048, 16384, 200, 7),    # band tiles of 16 rows
     (4096, 65536, 40, 8),     # the largest grid and sample count
+    (2048, 37, 300, 9),       # whole-circle walks with a row margin above 4095
+    (4096, 20, 200, 10),
 ])
 def test_sample_grid_bit_exact(aor, orc, G, J, n, seed):
     inst = synth.make_instance(n, 5100 + seed)
