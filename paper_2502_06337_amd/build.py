@@ -54,5 +54,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Device check programs that the GPU tests run (test code, not part of the library).
+CHECKS = {"recip_check": os.path.join(os.path.dirname(HERE), "tests", "recip_check.hip")}
+
+
+def build_checks(verbose: bool = False) -> list:
+    out = []
+    for name, src in CHECKS.items():
+        exe = os.path.join(os.path.dirname(src), name)
+        cmd = ["hipcc", *[f for f in FLAGS if f not in ("-fPIC",)], "-x", "hip", src, "-o", exe]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+            raise RuntimeError(f"check build failed: {' '.join(cmd)}\n{err}")
+        if verbose:
+            print("built", exe)
+        out.append(exe)
+    return out
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_checks(verbose=True)

@@ -46,6 +46,17 @@ namespace aoresp {
 
 // sigma * F-hat at (x, y): a, b, c already multiplied by sigma (exact negation).
 // xx = x*x and ax = a_loc*x are per-line terms.
+// Correctly rounded 1/x for x in [1, 4) (device only): the hardware
+// reciprocal (within an ulp) corrected by one fused Newton step.
+// tests/recip_check.hip compares it with the correctly rounded division for
+// every binary32 x in [1, 4) on the device; the sampling rule calls it with
+// x = 1 - s_z in [1, 2].
+__device__ __forceinline__ float recip_1_4(float x) {
+    const float y = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, y, 1.0f);
+    return __builtin_fmaf(e, y, y);
+}
+
 AOR_HD __forceinline__ float vertex_F(float b_loc, float c, float xx, float ax, float y) {
     float yy = y * y;
     float w = (xx + yy) - 1.0f;

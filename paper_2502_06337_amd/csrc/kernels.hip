@@ -834,7 +834,7 @@ __device__ __forceinline__ bool sample_cell(const float* a1, const float* a2, fl
     const float s1 = (a1[1] * c) + (a2[1] * sn);
     const float s2 = (a1[2] * c) + (a2[2] * sn);
     if (!(s2 <= 0.0f)) return false;
-    const float rinv = 1.0f / (1.0f - s2);
+    const float rinv = recip_1_4(1.0f - s2);
     const float u = s0 * rinv, v = s1 * rinv;
     ix = (int)floorf((u + 1.0f) * hg);
     iy = (int)floorf((v + 1.0f) * hg);
