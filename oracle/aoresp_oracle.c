@@ -312,7 +312,7 @@ OR_EXPORT void or_sample_grid(const float* P, const float* Q, long n, int G, int
 }
 
 /* ------------------------------------------------------------------------ */
-/* Peak search (Algorithm 1: "the block with the highest value")            */
+/* Peak search (Algorithm 1: the accumulator's maximum cell)                */
 /* ------------------------------------------------------------------------ */
 
 /* Argmax, ties to the lowest index.  Returns the maximum value. */

@@ -52,14 +52,13 @@ def est_rotation(P, Q, params=None, want_mask: bool = True):
     L = _lib.load()
     prm = _lib._params(params)
     res = Result()
+    P, Q = _lib._pair(P, Q)
     if _lib._is_torch(P):
         import torch
-        P, Q = _lib._dev_soa(P), _lib._dev_soa(Q)
         n = P.shape[1]
         mask = torch.empty(n, dtype=torch.uint8, device=P.device) if want_mask else None
         st = L.est_rotation_dev(_vp(P), _vp(Q), n, C.byref(prm), C.byref(res), _vp(mask), _lib._stream_ptr(P))
     else:
-        P, Q = _lib._host_soa(P), _lib._host_soa(Q)
         n = P.shape[1]
         mask = np.empty(n, dtype=np.uint8) if want_mask else None
         st = L.est_rotation(_vp(P), _vp(Q), n, C.byref(prm), C.byref(res), _vp(mask))
@@ -73,15 +72,14 @@ def est_rotations_topk(P, Q, k: int, params=None, want_mask: bool = True):
     prm = _lib._params(params)
     res = (Result * k)()
     found = C.c_uint32(0)
+    P, Q = _lib._pair(P, Q)
     if _lib._is_torch(P):
         import torch
-        P, Q = _lib._dev_soa(P), _lib._dev_soa(Q)
         n = P.shape[1]
         masks = torch.empty((k, n), dtype=torch.uint8, device=P.device) if want_mask else None
         st = L.est_rotations_topk_dev(_vp(P), _vp(Q), n, k, C.byref(prm), res, _vp(masks), C.byref(found),
                                       _lib._stream_ptr(P))
     else:
-        P, Q = _lib._host_soa(P), _lib._host_soa(Q)
         n = P.shape[1]
         masks = np.empty((k, n), dtype=np.uint8) if want_mask else None
         st = L.est_rotations_topk(_vp(P), _vp(Q), n, k, C.byref(prm), res, _vp(masks), C.byref(found))
@@ -95,7 +93,8 @@ def est_rotation_batch(P, Q, offsets, params=None, want_mask: bool = True):
     column offsets.  params: one entry or a list with one per instance.
     Returns (list of result dicts, mask (N,) or None, status)."""
     L = _lib.load()
-    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    P, Q = _lib._pair(P, Q)
+    off = _lib._offsets(offsets, P.shape[1])
     batch = off.size - 1
     if isinstance(params, (list, tuple)):
         prm_arr = (Params * len(params))(*[_lib._params(p) for p in params])
@@ -106,13 +105,11 @@ def est_rotation_batch(P, Q, offsets, params=None, want_mask: bool = True):
     res = (Result * max(batch, 1))()
     if _lib._is_torch(P):
         import torch
-        P, Q = _lib._dev_soa(P), _lib._dev_soa(Q)
         N = P.shape[1]
         mask = torch.empty(N, dtype=torch.uint8, device=P.device) if want_mask else None
         st = L.est_rotation_batch_dev(_vp(P), _vp(Q), off.ctypes.data, batch, prm_arr, pc, res, _vp(mask),
                                       _lib._stream_ptr(P))
     else:
-        P, Q = _lib._host_soa(P), _lib._host_soa(Q)
         N = P.shape[1]
         mask = np.empty(N, dtype=np.uint8) if want_mask else None
         st = L.est_rotation_batch(_vp(P), _vp(Q), off.ctypes.data, batch, prm_arr, pc, res, _vp(mask))
@@ -124,7 +121,9 @@ def coarse_grid(P, Q, G: int):
     """Axis accumulator of device tensors P, Q: (G, G) uint32 torch tensor (int32 view)."""
     import torch
     L = _lib.load()
-    P, Q = _lib._dev_soa(P), _lib._dev_soa(Q)
+    P, Q = _lib._pair(P, Q)
+    if not _lib._is_torch(P):
+        raise ValueError("coarse_grid takes torch CUDA tensors")
     grid = torch.empty((G, G), dtype=torch.int32, device=P.device)
     st = L.aoresp_coarse_grid_dev(_vp(P), _vp(Q), P.shape[1], G, _vp(grid), _lib._stream_ptr(P))
     _lib._check(st, "aoresp_coarse_grid_dev", allow=(OK,))
@@ -136,7 +135,9 @@ def solve_debug(P, Q, params=None):
     import torch
     L = _lib.load()
     prm = _lib._params(params)
-    P, Q = _lib._dev_soa(P), _lib._dev_soa(Q)
+    P, Q = _lib._pair(P, Q)
+    if not _lib._is_torch(P):
+        raise ValueError("solve_debug takes torch CUDA tensors")
     n = P.shape[1]
     G = prm.grid or grid_for_n(n)
     M = prm.refine_grid
@@ -166,7 +167,9 @@ class Server:
 
     def submit(self, P, Q, params=None) -> int:
         L = _lib.load()
-        P, Q = _lib._host_soa(P), _lib._host_soa(Q)
+        P, Q = _lib._pair(P, Q)
+        if _lib._is_torch(P):
+            raise ValueError("Server.submit takes host (numpy) arrays")
         prm = _lib._params(params)
         rid = C.c_uint64(0)
         _lib._check(L.aoresp_submit(self._h, P.ctypes.data, Q.ctypes.data, P.shape[1], C.byref(prm),
@@ -212,7 +215,9 @@ def autotune(P, Q, params=None) -> dict:
     of later solves are unchanged (bit-identical); only their speed is."""
     L = _lib.load()
     prm = _lib._params(params)
-    P, Q = _lib._dev_soa(P), _lib._dev_soa(Q)
+    P, Q = _lib._pair(P, Q)
+    if not _lib._is_torch(P):
+        raise ValueError("autotune takes torch CUDA tensors")
     out = _lib.Tuning()
     st = L.aoresp_autotune_dev(_vp(P), _vp(Q), P.shape[1], C.byref(prm), C.byref(out), _lib._stream_ptr(P))
     if st != OK:

@@ -183,3 +183,36 @@ def _dev_soa(t):
     if t.dtype != torch.float32 or t.dim() != 2 or t.shape[0] != 3 or not t.is_cuda:
         raise ValueError("expected a (3, n) float32 CUDA tensor")
     return t.contiguous()
+
+
+def _pair(P, Q):
+    """P and Q as one host pair or one device pair of equal (3, n) shape: the
+    library reads n columns of both, so a shorter Q would be read past its
+    end."""
+    if _is_torch(P) != _is_torch(Q):
+        raise ValueError("P and Q must both be numpy arrays or both be torch tensors")
+    if _is_torch(P):
+        P, Q = _dev_soa(P), _dev_soa(Q)
+        if P.device != Q.device:
+            raise ValueError(f"P and Q are on different devices ({P.device}, {Q.device})")
+    else:
+        P, Q = _host_soa(P), _host_soa(Q)
+    if P.shape != Q.shape:
+        raise ValueError(f"P and Q must have the same shape, got {tuple(P.shape)} and {tuple(Q.shape)}")
+    return P, Q
+
+
+def _offsets(offsets, ncols: int) -> np.ndarray:
+    """Batch column offsets: batch + 1 non-decreasing entries from 0 to the
+    number of columns of P and Q."""
+    off = np.asarray(offsets)
+    if off.ndim != 1 or off.size < 2:
+        raise ValueError("offsets must be a 1-D sequence of batch + 1 column offsets")
+    if not np.issubdtype(off.dtype, np.integer):
+        raise ValueError("offsets must be integers")
+    if int(off[0]) != 0 or int(off[-1]) != int(ncols):
+        raise ValueError(f"offsets must run from 0 to {ncols} (the columns of P and Q), got "
+                         f"{int(off[0])} .. {int(off[-1])}")
+    if (np.diff(off.astype(np.int64)) < 0).any():
+        raise ValueError("offsets must not decrease")
+    return np.ascontiguousarray(off, dtype=np.uint64)

@@ -754,9 +754,7 @@ aoresp_status aoresp_coarse_grid_dev(const float* P, const float* Q, size_t n, u
     if (!grid || (n > 0 && (!P || !Q)) || n > (size_t)INT32_MAX) return AORESP_EINVAL;
     if (!is_pow2(G) || G < 64 || G > 4096) return AORESP_EINVAL;
     hipStream_t s = (hipStream_t)hip_stream;
-    if (n < 2) {
-        // fewer than two correspondences still vote: run the vote path alone
-    }
+    // a single correspondence still votes: n = 1 runs the vote path like any n
     aoresp_params prm{};
     prm.grid = G;
     aoresp_result out;

@@ -44,8 +44,6 @@
 
 namespace aoresp {
 
-// sigma * F-hat at (x, y): a, b, c already multiplied by sigma (exact negation).
-// xx = x*x and ax = a_loc*x are per-line terms.
 // Correctly rounded 1/x for x in [1, 4) (device only): the hardware
 // reciprocal (within an ulp) corrected by one fused Newton step.
 // tests/recip_check.hip compares it with the correctly rounded division for
@@ -57,6 +55,8 @@ __device__ __forceinline__ float recip_1_4(float x) {
     return __builtin_fmaf(e, y, y);
 }
 
+// sigma * F-hat at (x, y): a, b, c already multiplied by sigma (exact negation).
+// xx = x*x and ax = a_loc*x are per-line terms.
 AOR_HD __forceinline__ float vertex_F(float b_loc, float c, float xx, float ax, float y) {
     float yy = y * y;
     float w = (xx + yy) - 1.0f;

@@ -1670,11 +1670,14 @@ SampleLayout sample_plan(int G, int J, int64_t n) {
     // 16-bit counters when one item cannot carry a counter: the samples one
     // circle puts in one cell lie on an arc inside the cell, shorter than
     // 1.01 times its diagonal sqrt(2) h (a circle of radius >= 1 through a cell
-    // of side h <= 1/32), and consecutive southern samples are at least
-    // 0.45 dtheta apart in the plane (the projection shrinks lengths by at most
-    // 2, and the chord of such a short arc is within 1% of it), so at most
-    // 1 + sqrt(2) 1.01 h / (0.45 dtheta) = 1 + 1.01 J / G samples; an item of
-    // at most 65535 / that many circles cannot overflow.
+    // of side h = 2/G <= 1/32).  Consecutive southern samples are at least
+    // 0.495 dtheta apart in the plane (dtheta = 2 pi / J): on the southern half
+    // the projection scales lengths by 1/(1 - s_z) >= 1/2, and for J >= 64 the
+    // chord of one sample step is within 1% of its arc, on the sphere and in
+    // the plane.  So a cell takes at most
+    // 1 + 1.01 sqrt(2) h / (0.495 dtheta) = 1 + 0.919 J / G samples per
+    // circle; spc below uses the larger 1 + ceil(1.01 J / G), and an item of
+    // at most 65535 / spc circles cannot overflow.
     const int64_t spc = 1 + (int64_t)std::ceil(1.01 * (double)J / (double)G);
     const int64_t cap16 = (65535 / spc) / 16 * 16;
     if (J >= 64 && cap16 >= 1024) {

@@ -63,3 +63,41 @@ def test_bench_refuses_several_gpus():
                        text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+def test_binding_rejects_mismatched_inputs():
+    """Shapes, kinds and batch offsets are checked before any call into the
+    library: n comes from P, so a shorter Q would be read past its end."""
+    import paper_2502_06337_amd as aor
+    P = np.zeros((3, 10), dtype=np.float32)
+    with pytest.raises(ValueError, match="same shape"):
+        aor.est_rotation(P, np.zeros((3, 9), dtype=np.float32))
+    with pytest.raises(ValueError, match="same shape"):
+        aor.est_rotations_topk(P, np.zeros((3, 11), dtype=np.float32), 2)
+    with pytest.raises(ValueError, match="same shape"):
+        aor.est_rotation_batch(P, np.zeros((3, 9), dtype=np.float32), [0, 5, 10])
+    with pytest.raises(ValueError, match=r"\(3, n\)"):
+        aor.est_rotation(np.zeros((4, 10), dtype=np.float32), np.zeros((4, 10), dtype=np.float32))
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError, match="both"):
+        aor.est_rotation(P, torch.zeros((3, 10), dtype=torch.float32))
+    with pytest.raises(ValueError, match="CUDA"):
+        aor.est_rotation(torch.zeros((3, 10)), torch.zeros((3, 10)))
+
+
+def test_binding_rejects_bad_batch_offsets():
+    import paper_2502_06337_amd as aor
+    P = np.zeros((3, 10), dtype=np.float32)
+    Q = np.zeros((3, 10), dtype=np.float32)
+    with pytest.raises(ValueError, match="run from 0 to 10"):
+        aor.est_rotation_batch(P, Q, [0, 5, 9])       # total below the columns
+    with pytest.raises(ValueError, match="run from 0 to 10"):
+        aor.est_rotation_batch(P, Q, [0, 5, 12])      # total beyond them
+    with pytest.raises(ValueError, match="run from 0 to 10"):
+        aor.est_rotation_batch(P, Q, [1, 5, 10])
+    with pytest.raises(ValueError, match="not decrease"):
+        aor.est_rotation_batch(P, Q, [0, 7, 3, 10])
+    with pytest.raises(ValueError, match="integers"):
+        aor.est_rotation_batch(P, Q, [0.0, 10.0])
+    with pytest.raises(ValueError, match="batch"):
+        aor.est_rotation_batch(P, Q, [10])

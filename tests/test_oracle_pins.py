@@ -782,3 +782,92 @@ def test_angle_window_repeats_bins_when_B_below_3(orc):
     assert np.array_equal(out["fine_hist"], full[win])
     assert out["angle_fine_bin"] == win[int(np.argmax(full[win]))]
     assert out["fine_hist"][:F].tolist() == out["fine_hist"][2 * F:].tolist()   # bins k-1 and k+1 coincide
+
+
+# ------------------------------------------- refinement -> axis (Eq. (8))
+def _axis_rotation(r, theta):
+    """Rotation by theta about unit axis r (textbook Rodrigues, float64)."""
+    r = np.asarray(r, dtype=np.float64)
+    K = np.array([[0.0, -r[2], r[1]], [r[2], 0.0, -r[0]], [-r[1], r[0], 0.0]])
+    return np.eye(3) + math.sin(theta) * K + (1.0 - math.cos(theta)) * (K @ K)
+
+
+# (u*, v*) in units of the coarse step h from the grid's lower-left corner
+# (-1, -1) is not used: the points are given directly in the plane.  Central,
+# left rim (window clipped to nx = 2), bottom rim (ny = 2), right rim (nx = 2).
+_REFINE_POINTS = {
+    "central": lambda h: (0.1234, -0.2345),
+    "left_rim": lambda h: (-1.0 + 0.37 * h, 0.2 * h),
+    "bottom_rim": lambda h: (0.15 * h, -1.0 + 0.41 * h),
+    "right_rim": lambda h: (1.0 - 0.45 * h, -0.1 * h),
+}
+
+
+@pytest.mark.parametrize("M", [16, 64])
+@pytest.mark.parametrize("where", sorted(_REFINE_POINTS))
+def test_refined_peak_is_the_projected_axis(orc, where, M):
+    """Refinement then back-projection (Sec. IV-A, Eq. (8)).  Noise-free pairs
+    q = R p about an axis r whose projection (u*, v*) is known: every great
+    circle passes through r, so every projected curve passes through (u*, v*).
+    The refined cell must be the fine cell holding (u*, v*) or a neighbour,
+    i.e. its centre within 1.5 fine steps of (u*, v*) in each coordinate, and
+    the axis within the matching distance on the sphere (the projection's
+    inverse stretches plane lengths by at most 2 inside the disk).  At the rim
+    the coarse window is clipped, so the fine steps differ in u and v
+    (hx != hy): a fine centre built with the steps swapped lands about half
+    a coarse cell away and fails the test."""
+    G, B, n = 128, 360, 240
+    h = 2.0 / G
+    u, v = _REFINE_POINTS[where](h)
+    assert u * u + v * v < 1.0
+    s = u * u + v * v
+    r = np.array([2 * u, 2 * v, s - 1.0]) / (1.0 + s)     # E8, the southern axis
+    R = _axis_rotation(r, 0.7)
+    P = (synth.uniform_f64(4242, 0, 3 * n).reshape(3, n) * 2.0 - 1.0)
+    Q = R @ P
+    P32, Q32 = P.astype(np.float32), Q.astype(np.float32)
+    res = orc.solve(P32, Q32, G=G, B=B, M=M, w=1, want_grids=True)
+    assert res["status"] == 0
+    ix, iy = res["peak_cell"] % G, res["peak_cell"] // G
+    win = orc.fine_window(G, M, 1, ix, iy)
+    # the coarse peak holds the axis (or a neighbour of its cell), so the
+    # window covers it
+    assert win.U0 <= u <= win.U0 + win.nx * h and win.V0 <= v <= win.V0 + win.ny * h
+    if where != "central":
+        assert (win.nx, win.ny) != (3, 3), "the rim window must be clipped"
+    jx, jy = res["fine_cell"] % M, res["fine_cell"] // M
+    uc, vc = orc.fine_center(win, jx, jy)
+    hx, hy = win.nx * h / M, win.ny * h / M
+    assert abs(float(uc) - u) <= 1.5 * hx and abs(float(vc) - v) <= 1.5 * hy, (where, jx, jy, uc, vc, u, v)
+    # most curves vote for the refined cell (the corner rule can miss an arc
+    # that enters and leaves a cell through one edge)
+    assert res["fine_votes"] >= 0.9 * n
+    ax = res["axis"].astype(np.float64)
+    err = min(np.linalg.norm(ax - r), np.linalg.norm(ax + r))
+    assert err <= 2.0 * 1.5 * math.hypot(hx, hy) + 1e-6, (where, err)
+    # strictly finer than the coarse-cell bound
+    assert err < math.sqrt(2) * h
+
+
+def test_refined_axis_beats_coarse_axis(orc):
+    """The same noise-free data with and without refinement: the refined axis
+    is closer to the generating axis than the coarse cell centre on average
+    over several axes."""
+    G, B, n = 128, 360, 200
+    h = 2.0 / G
+    coarse, fine = [], []
+    for t in range(6):
+        u = -0.6 + 0.23 * t + 0.011
+        v = 0.4 - 0.17 * t + 0.007
+        s = u * u + v * v
+        r = np.array([2 * u, 2 * v, s - 1.0]) / (1.0 + s)
+        R = _axis_rotation(r, 0.3 + 0.2 * t)
+        P = synth.uniform_f64(77 + t, 0, 3 * n).reshape(3, n) * 2.0 - 1.0
+        Q = (R @ P).astype(np.float32)
+        P = P.astype(np.float32)
+        for M, acc in ((0, coarse), (64, fine)):
+            out = orc.solve(P, Q, G=G, B=B, M=M)
+            ax = out["axis"].astype(np.float64)
+            acc.append(min(np.linalg.norm(ax - r), np.linalg.norm(ax + r)))
+    assert np.mean(fine) < 0.25 * np.mean(coarse), (coarse, fine)
+    assert max(fine) < 3.0 * 1.5 * math.hypot(3 * h / 64, 3 * h / 64)
