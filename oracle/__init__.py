@@ -109,6 +109,7 @@ def lib():
             "or_inliers": (C.c_long, [_fp, _fp, _fp, C.c_long, _f, _u8p]),
             "or_rotation_error_deg": (C.c_double, [C.POINTER(C.c_double), _fp]),
             "or_suppressed": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),
+            "or_local_max": (C.c_int, [_u32p, C.c_int, C.c_int, C.c_int, C.c_int]),
             "or_topk_peaks": (C.c_int, [_u32p, C.c_int, C.c_int, C.c_int, _lp, _u32p]),
             "or_finish_peak": (None, [_fp, _fp, C.c_long, C.c_int, C.c_int, C.c_int, C.c_int, _f,
                                       C.c_long, C.c_uint32, C.POINTER(Result), _u8p, _u32p, _u32p]),
@@ -370,6 +371,11 @@ def ls_rotation(P, Q, mask) -> np.ndarray:
 
 def suppressed(G: int, rad: int, px: int, py: int, ix: int, iy: int) -> bool:
     return bool(lib().or_suppressed(G, rad, px, py, ix, iy))
+
+
+def local_max(grid, rad: int, ix: int, iy: int) -> bool:
+    grid = np.ascontiguousarray(grid, dtype=np.uint32)
+    return bool(lib().or_local_max(_ptr(grid.ravel(), _u32p), grid.shape[0], rad, ix, iy))
 
 
 def topk_peaks(grid, k: int, rad: int):

@@ -38,6 +38,10 @@
  *     the signs of F at its four corners: it is voted iff it meets the closed
  *     unit disk, some corner has F <= 0 and some corner has F >= 0.
  *   - ties in every argmax go to the lowest index.
+ *   - several rotations (Sec. IV-D): the peaks are the accumulator's local
+ *     maxima within the suppression radius, taken by decreasing votes; a cell
+ *     within that radius of a peak already taken, or of its antipodal twin
+ *     at the rim, is skipped.
  *   - the angle is signed, theta = atan2(r.(p x q), (r x p).(r x q)), binned
  *     over [-pi, pi) without transcendental functions: by comparison with a
  *     table of bin-boundary directions.
@@ -615,7 +619,33 @@ OR_EXPORT int or_suppressed(int G, int rad, int px, int py, int ix, int iy) {
     return d2 <= rr;
 }
 
-/* Greedy top-k over the coarse grid.  Returns the number of peaks found. */
+/* Is coarse cell (ix, iy) a local maximum of the accumulator within the
+ * integer disk of radius rad?  Every other cell of the grid in that disk must
+ * hold fewer votes, or as many at a higher linear index (the tie-break of the
+ * argmax).  This is what non-maximum suppression means for peak detection: the
+ * flank of a strong peak is never a peak of its own, however far from the
+ * summit the flank reaches. */
+OR_EXPORT int or_local_max(const uint32_t* grid, int G, int rad, int ix, int iy) {
+    long c = (long)iy * G + ix;
+    for (int dy = -rad; dy <= rad; ++dy) {
+        for (int dx = -rad; dx <= rad; ++dx) {
+            if (dx == 0 && dy == 0) continue;
+            if ((long)dx * dx + (long)dy * dy > (long)rad * rad) continue;
+            int jx = ix + dx, jy = iy + dy;
+            if (jx < 0 || jx >= G || jy < 0 || jy >= G) continue;
+            long o = (long)jy * G + jx;
+            if (grid[o] > grid[c]) return 0;
+            if (grid[o] == grid[c] && o < c) return 0;
+        }
+    }
+    return 1;
+}
+
+/* Top-k over the coarse grid (Sec. IV-D): in order of decreasing votes (ties to
+ * the lowest index), the cells with at least one vote that are local maxima
+ * within radius rad and are not suppressed by a peak already taken (its disk,
+ * or the disk around its antipodal twin at the rim).  Returns the number of
+ * peaks found. */
 OR_EXPORT int or_topk_peaks(const uint32_t* grid, int G, int k, int rad, long* peaks, uint32_t* votes) {
     int found = 0;
     for (int t = 0; t < k; ++t) {
@@ -623,11 +653,14 @@ OR_EXPORT int or_topk_peaks(const uint32_t* grid, int G, int k, int rad, long* p
         long bi = -1;
         for (long c = 0; c < (long)G * G; ++c) {
             int ix = (int)(c % G), iy = (int)(c / G);
+            if (grid[c] <= best) continue;
+            if (!or_local_max(grid, G, rad, ix, iy)) continue;
             int sup = 0;
             for (int s = 0; s < found && !sup; ++s)
                 sup = or_suppressed(G, rad, (int)(peaks[s] % G), (int)(peaks[s] / G), ix, iy);
             if (sup) continue;
-            if (grid[c] > best) { best = grid[c]; bi = c; }
+            best = grid[c];
+            bi = c;
         }
         if (bi < 0 || best == 0) break;
         peaks[found] = bi;

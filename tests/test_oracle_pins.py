@@ -426,6 +426,108 @@ def test_topk_recovers_three_rotations(orc):
         assert best < 5.0
 
 
+def _cone_grid(G, peaks):
+    """Sum of integer cones max(0, height - slope * distance), one per
+    (ix, iy, height, slope); distances in cells, rounded down."""
+    iy, ix = np.mgrid[0:G, 0:G]
+    g = np.zeros((G, G), np.int64)
+    for px, py, hgt, slope in peaks:
+        d = np.floor(np.hypot(ix - px, iy - py)).astype(np.int64)
+        g += np.maximum(0, hgt - slope * d)
+    return g.astype(np.uint32)
+
+
+def test_topk_peaks_are_local_maxima_not_flanks(orc):
+    """Sec. IV-D: a broad peak's flank is no second peak.  A cone of height 100
+    falling 10 per cell at (20, 20) and an isolated bump of 30 at (45, 40): the
+    cone's cells 6 cells out hold 40 votes, more than the bump, but each has a
+    higher neighbour within the radius, so the second peak is the bump and a
+    third does not exist."""
+    G, rad = 64, 5
+    g = _cone_grid(G, [(20, 20, 100, 10), (45, 40, 30, 100)])
+    assert g[20 + 6, 20] == 40 and g[40, 45] == 30
+    peaks = orc.topk_peaks(g, 3, rad)
+    assert peaks == [(20 * G + 20, 100), (40 * G + 45, 30)]
+    assert orc.local_max(g, rad, 20, 20) and orc.local_max(g, rad, 45, 40)
+    assert not orc.local_max(g, rad, 20, 26)
+
+
+def test_topk_local_max_ties_and_radius(orc):
+    """Equal neighbours: only the lower linear index is a local maximum.  A
+    cell beats every cell of its disk; a cell just outside the disk does not
+    count (disk of radius 3: offset (3, 0) inside, (3, 1) outside)."""
+    G, rad = 32, 3
+    g = np.zeros((G, G), np.uint32)
+    g[10, 10] = g[10, 11] = 7
+    assert orc.local_max(g, rad, 10, 10) and not orc.local_max(g, rad, 11, 10)
+    assert orc.topk_peaks(g, 2, rad) == [(10 * G + 10, 7)]
+    g = np.zeros((G, G), np.uint32)
+    g[16, 16] = 5
+    g[16, 19] = 9
+    assert not orc.local_max(g, rad, 16, 16)
+    g = np.zeros((G, G), np.uint32)
+    g[16, 16] = 5
+    g[17, 19] = 9
+    assert orc.local_max(g, rad, 16, 16)
+    assert orc.topk_peaks(g, 3, rad) == [(17 * G + 19, 9), (16 * G + 16, 5)]
+
+
+def _rot_axis_angle(axis, t):
+    a = np.asarray(axis, np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+    return np.eye(3) + math.sin(t) * K + (1 - math.cos(t)) * (K @ K)
+
+
+def _axis_of_uv(u, v):
+    s = u * u + v * v
+    return np.array([2 * u, 2 * v, s - 1]) / (1 + s)
+
+
+def test_topk_rim_axis_beside_broad_peak(orc):
+    """Three rotations (Sec. IV-D; Sec. V-B's multi-rotation setup): a strong
+    rotation whose noisy inliers (sigma = 0.04) spread its peak past the 5-cell
+    radius, and two weaker ones, one with its axis 2.5 cells from the disk rim.
+    At G = 128 every rotation is recovered: the first peak's flank, which
+    outvotes the rim axis, is not a local maximum."""
+    G, rad, n = 128, 5, 20000
+    rng = np.random.default_rng(77)
+    P = rng.uniform(-1, 1, (3, n))
+    Q = rng.uniform(-1, 1, (3, n))
+    h = 2.0 / G
+    spec = [((0.05, -0.1), 1.0, 8000), ((-0.45, 0.35), -2.0, 2400), ((1 - 2.5 * h, 0.02), 2.4, 2400)]
+    perm = rng.permutation(n)
+    Rs, st = [], 0
+    for (u, v), t, cnt in spec:
+        R = _rot_axis_angle(_axis_of_uv(u, v), t)
+        idx = perm[st:st + cnt]
+        st += cnt
+        Q[:, idx] = R @ P[:, idx] + 0.04 * rng.standard_normal((3, cnt))
+        Rs.append(R)
+    P = P.astype(np.float32)
+    Q = Q.astype(np.float32)
+    g = orc.coarse_grid(P, Q, G)
+    peaks = orc.topk_peaks(g, 3, rad)
+    assert len(peaks) == 3
+    # the flank of the first peak outvotes the rim axis's peak
+    (c0, v0), (c2, v2) = peaks[0], peaks[2]
+    px, py = c0 % G, c0 // G
+    flank = [g[y, x] for y in range(G) for x in range(G)
+             if rad * rad < (x - px) ** 2 + (y - py) ** 2 <= (rad + 2) ** 2]
+    assert max(flank) > v2
+    # the third peak is the rim axis's cell or a neighbour
+    ru = (1 - 2.5 * h + 1) / h
+    assert abs(c2 % G - ru) <= 2 and abs(c2 // G - (0.02 + 1) / h) <= 2
+    # peaks are pairwise farther apart than the radius, each the maximum of its disk
+    for i in range(3):
+        for j in range(i):
+            a, b = peaks[i][0], peaks[j][0]
+            assert (a % G - b % G) ** 2 + (a // G - b // G) ** 2 > rad * rad
+    out = orc.solve_topk(P, Q, G=G, B=360, k=3, rad=rad)
+    for R in Rs:
+        assert min(orc.rotation_error_deg(R, o["R"]) for o in out) < 1.5
+
+
 def test_enodata(orc):
     P = np.zeros((3, 1), dtype=np.float32)
     res = orc.solve(P, P, G=64, B=36)
