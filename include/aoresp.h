@@ -106,9 +106,12 @@ aoresp_status est_rotation(const float* P, const float* Q, size_t n, const aores
 aoresp_status est_rotation_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
                                aoresp_result* out, uint8_t* inlier_mask, void* hip_stream);
 
-/* Several rotations (Sec. IV-D): greedy top-k peaks with suppression of a
- * disk of nms_radius cells around each earlier peak and of the disk of radius
- * nms_radius*h around the projection of its antipodal axis.  out: k entries;
+/* Several rotations (Sec. IV-D): the peaks are the accumulator's local maxima
+ * within an integer disk of nms_radius cells (every other cell of the disk
+ * holds fewer votes, or as many at a higher index), taken by decreasing votes
+ * (ties to the lowest index); a cell within the disk of an earlier peak or
+ * within nms_radius*h of the projection of its antipodal axis is skipped.
+ * The first peak is the global maximum, as in est_rotation.  out: k entries;
  * masks: k*n bytes (row t = peak t) or NULL; *k_found = peaks found (<= k).
  * k in [1, 8]. */
 aoresp_status est_rotations_topk(const float* P, const float* Q, size_t n, uint32_t k,

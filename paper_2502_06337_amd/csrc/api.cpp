@@ -66,6 +66,7 @@ aoresp_status resolve_params(const aoresp_params* prm, size_t n, ResolvedParams&
 
 aoresp_status DevBuf::ensure(size_t need) {
     if (need <= bytes) return AORESP_OK;
+    if (fixed) return AORESP_ENOMEM;
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -80,6 +81,7 @@ aoresp_status DevBuf::ensure(size_t need) {
 }
 
 void DevBuf::release() {
+    if (fixed) return;
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -98,21 +100,24 @@ DeviceCtx* device_ctx() {
     ctx->device = dev;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) ctx->cu_count = prop.multiProcessorCount;
-    if (hipStreamCreateWithFlags(&ctx->ws.stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
-    if (hipStreamCreateWithFlags(&ctx->ws.cap_stream, hipStreamNonBlocking) != hipSuccess) return nullptr;
     init_kernel_attributes();
     DeviceCtx* raw = ctx.get();
     g_ctx[dev] = std::move(ctx);
     return raw;
 }
 
+hipStream_t internal_stream(DeviceCtx* ctx) {
+    // callers hold ctx->mu
+    if (!ctx->ws.stream && hipStreamCreateWithFlags(&ctx->ws.stream, hipStreamNonBlocking) != hipSuccess) {
+        ctx->ws.stream = nullptr;
+        (void)hipGetLastError();
+    }
+    return ctx->ws.stream;
+}
+
 // Angle tables: boundary k at phi_k = -pi + k * (2 pi / B) and bin centres
 // -pi + (k + 1/2) (2 pi / B), evaluated in double and rounded once to float.
-const AngleTables* angle_tables(DeviceCtx* ctx, int B) {
-    std::lock_guard<std::mutex> lk(ctx->table_mu);
-    auto it = ctx->angle.find(B);
-    if (it != ctx->angle.end()) return &it->second;
-    std::vector<float> h(5 * (size_t)B);
+void fill_angle_tables(float* h, int B) {
     const double step = (2.0 * M_PI) / (double)B;
     for (int k = 0; k < B; ++k) {
         double phi = -M_PI + (double)k * step;
@@ -123,26 +128,34 @@ const AngleTables* angle_tables(DeviceCtx* ctx, int B) {
         h[3 * B + k] = (float)std::cos(ph);
         h[4 * B + k] = (float)std::sin(ph);
     }
-    float* d = nullptr;
-    if (hipMalloc((void**)&d, h.size() * sizeof(float)) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+}
+
+static AngleTables split_angle_tables(float* d, int B) {
     AngleTables t;
     t.tc = d;
     t.ts = d + B;
     t.th = d + 2 * B;
     t.ct = d + 3 * B;
     t.st = d + 4 * B;
-    return &(ctx->angle[B] = t);
+    return t;
+}
+
+const AngleTables* angle_tables(DeviceCtx* ctx, int B) {
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
+    auto it = ctx->angle.find(B);
+    if (it != ctx->angle.end()) return &it->second;
+    std::vector<float> h(5 * (size_t)B);
+    fill_angle_tables(h.data(), B);
+    float* d = nullptr;
+    if (hipMalloc((void**)&d, h.size() * sizeof(float)) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    return &(ctx->angle[B] = split_angle_tables(d, B));
 }
 
 // In-disk cross range of every cell line of a G x G grid over [-1, 1]^2: cell
 // (j, k) meets the closed unit disk iff min over its corners of
 // u^2 + v^2 - 1 <= 0; with u = (2j - G)/G this is an integer test.
-const int16_t* disk_table(DeviceCtx* ctx, int G) {
-    std::lock_guard<std::mutex> lk(ctx->table_mu);
-    auto it = ctx->disk.find(G);
-    if (it != ctx->disk.end()) return it->second;
-    std::vector<int16_t> h(2 * (size_t)G);
+void fill_disk_table(int16_t* h, int G) {
     auto mind = [G](int j) {
         long a = std::labs(2L * j - G), b = std::labs(2L * j + 2 - G);
         return a < b ? a : b;
@@ -161,6 +174,14 @@ const int16_t* disk_table(DeviceCtx* ctx, int G) {
         h[2 * j] = (int16_t)lo;
         h[2 * j + 1] = (int16_t)hi;
     }
+}
+
+const int16_t* disk_table(DeviceCtx* ctx, int G) {
+    std::lock_guard<std::mutex> lk(ctx->table_mu);
+    auto it = ctx->disk.find(G);
+    if (it != ctx->disk.end()) return it->second;
+    std::vector<int16_t> h(2 * (size_t)G);
+    fill_disk_table(h.data(), G);
     int16_t* d = nullptr;
     if (hipMalloc((void**)&d, h.size() * sizeof(int16_t)) != hipSuccess) return nullptr;
     if (hipMemcpy(d, h.data(), h.size() * sizeof(int16_t), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
@@ -168,8 +189,32 @@ const int16_t* disk_table(DeviceCtx* ctx, int G) {
     return d;
 }
 
+const AngleTables* TableSink::angle_tables(int B) {
+    for (int i = 0; i < nangle; ++i)
+        if (angle_B[i] == B) return &angle[i];
+    const size_t bytes = (5 * (size_t)B * sizeof(float) + 255) / 256 * 256;
+    if (nangle == 4 || used + bytes > cap) return nullptr;
+    fill_angle_tables(reinterpret_cast<float*>(host + used), B);
+    angle_B[nangle] = B;
+    angle[nangle] = split_angle_tables(reinterpret_cast<float*>(dev + used), B);
+    used += bytes;
+    return &angle[nangle++];
+}
+
+const int16_t* TableSink::disk_table(int G) {
+    if (disk) return disk_G == G ? disk : nullptr;
+    const size_t bytes = (2 * (size_t)G * sizeof(int16_t) + 255) / 256 * 256;
+    if (used + bytes > cap) return nullptr;
+    fill_disk_table(reinterpret_cast<int16_t*>(host + used), G);
+    disk_G = G;
+    disk = reinterpret_cast<const int16_t*>(dev + used);
+    used += bytes;
+    return disk;
+}
+
 aoresp_status HostBuf::ensure(size_t need) {
     if (need <= bytes) return AORESP_OK;
+    if (fixed) return AORESP_ENOMEM;
     if (ptr) (void)hipHostFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -212,7 +257,8 @@ aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const Re
 }
 
 aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps, const int* npk,
-                              const Tuning* force, Plan& plan) {
+                              const Tuning* force, Plan& plan, TableSink* tables) {
+    auto angle_of = [ctx, tables](int B) { return tables ? tables->angle_tables(B) : angle_tables(ctx, B); };
     plan = Plan();
     plan.insts.resize(ninst);
     std::vector<std::pair<double, int4>> votes, samples;
@@ -236,14 +282,16 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         plan.nres += I.npk;
         I.grid_off = (int64_t)plan.grid_cells;
         plan.grid_cells += (size_t)rp.G * rp.G;
+        I.lmax_off = (int64_t)plan.lmax_words;
+        if (npk[b] > 1) plan.lmax_words += (size_t)rp.G * rp.G / 32;
         I.fine_off = (int64_t)plan.fine_cells;
         plan.fine_cells += (size_t)I.npk * rp.M * rp.M;
         I.hist_off = (int64_t)plan.hist_cells;
         plan.hist_cells += (size_t)I.npk * rp.B;
         I.item0 = (int32_t)plan.corr_items.size();
         I.nitems = 0;
-        const AngleTables* at = angle_tables(ctx, rp.B);
-        const int16_t* disk = disk_table(ctx, rp.G);
+        const AngleTables* at = angle_of(rp.B);
+        const int16_t* disk = tables ? tables->disk_table(rp.G) : disk_table(ctx, rp.G);
         if (!at || !disk) return AORESP_ENOMEM;
         I.disk = disk;
         I.tc = at->tc;
@@ -259,7 +307,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         I.gate = rp.gate;
         I.F = rp.F;
         if (rp.F > 1) {
-            const AngleTables* ft = angle_tables(ctx, rp.B * rp.F);
+            const AngleTables* ft = angle_of(rp.B * rp.F);
             if (!ft) return AORESP_ENOMEM;
             I.ftc = ft->tc;
             I.fts = ft->ts;
@@ -275,7 +323,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         I.rule = rp.rule;
         I.J = rp.J;
         if (rp.rule == 1) {
-            const AngleTables* sd = angle_tables(ctx, rp.J);   // cos, sin of -pi + j 2pi/J
+            const AngleTables* sd = angle_of(rp.J);   // cos, sin of -pi + j 2pi/J
             if (!sd) return AORESP_ENOMEM;
             I.scs = sd->tc;
             I.ssn = sd->ts;
@@ -369,26 +417,12 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
                            uint32_t* hist_out) {
     const int64_t N = plan.N;
     const int ninst = (int)plan.insts.size();
-    const size_t nn = N > 0 ? (size_t)N : 1;
     aoresp_status st;
     auto mark = [&](int k) {
         if (marks) (void)hipEventRecord(marks[k], s);
     };
-    if ((st = w.abc.ensure(nn * sizeof(float4))) != AORESP_OK) return st;
-    if ((st = w.colp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = w.rowp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = w.geo.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = w.grid.ensure(plan.grid_cells * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.hist.ensure((plan.hist_cells + plan.fhist_cells) * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
+    if ((st = reserve_plan(w, plan)) != AORESP_OK) return st;
     const OutLayout ol(plan.nres);
-    if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
-    if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
-    if ((st = w.lsum.ensure((plan.corr_items.size() + 1) * kLsWords * sizeof(double))) != AORESP_OK) return st;
-    if ((st = w.srec.ensure(plan.sample_recs * kSampleRec * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.spart.ensure(plan.sample_part * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
     const size_t o_vote = (b_inst + 255) / 256 * 256;
@@ -398,8 +432,6 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     const size_t o_sset = o_list + plan.list_items.size() * sizeof(int4);
     const size_t o_samp = o_sset + plan.sample_setup_items.size() * sizeof(int4);
     const size_t total = plan_blob_bytes(plan);
-    if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
-    if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
     char* hb = w.h_plan.as<char>();
     std::memcpy(hb, plan.insts.data(), b_inst);
     if (!plan.vote_items.empty())
@@ -455,8 +487,12 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
                        (int)plan.sample_items.size(), cell_items, (int)plan.cell_items.size(), w.srec.as<uint32_t>(),
                        w.spart.as<uint32_t>(), w.grid.as<uint32_t>(), plan.sample_lds, s);
     mark(2);
+    if (plan.max_npk > 1)
+        launch_local_max(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), w.lmax.as<uint32_t>(),
+                         s);
     for (int t = 0; t < plan.max_npk; ++t) {
-        launch_peak(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), stt, t, keys, s);
+        launch_peak(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), stt, t,
+                    w.lmax.as<uint32_t>(), keys, s);
         launch_peak_finish(insts, ninst, keys, stt, t, s);
     }
     mark(3);
@@ -574,29 +610,40 @@ aoresp_status launch_plan_graph(DeviceCtx* ctx, Workspace& w, const Plan& plan, 
     return AORESP_OK;
 }
 
+void plan_buffers(Workspace& w, const Plan& plan, BufNeed* out) {
+    const size_t nn = plan.N > 0 ? (size_t)plan.N : 1;
+    const OutLayout ol(plan.nres);
+    const BufNeed list[kPlanBuffers] = {
+        {&w.abc, nn * sizeof(float4)},
+        {&w.colp, nn * sizeof(int4)},
+        {&w.rowp, nn * sizeof(int4)},
+        {&w.geo, nn * sizeof(int4)},
+        {&w.grid, plan.grid_cells * 4 + 4},
+        {&w.fine, plan.fine_cells * 4 + 4},
+        {&w.hist, (plan.hist_cells + plan.fhist_cells) * 4 + 4},
+        {&w.keys, (size_t)plan.nres * 8},
+        {&w.lmax, plan.lmax_words * 4 + 4},
+        {&w.out, ol.bytes},
+        {&w.icount, (size_t)plan.nres * kCountSlots * 4},
+        {&w.lsum, (plan.corr_items.size() + 1) * kLsWords * sizeof(double)},
+        {&w.srec, plan.sample_recs * kSampleRec * 4 + 4},
+        {&w.spart, plan.sample_part * 4 + 4},
+        {&w.plan, plan_blob_bytes(plan)},
+    };
+    for (int i = 0; i < kPlanBuffers; ++i) out[i] = list[i];
+}
+
 // All device and pinned buffers a plan needs (the allocation half of
 // enqueue_plan and fetch_plan).
 aoresp_status reserve_plan(Workspace& w, const Plan& plan) {
-    const size_t nn = plan.N > 0 ? (size_t)plan.N : 1;
+    BufNeed need[kPlanBuffers];
+    plan_buffers(w, plan, need);
     aoresp_status st;
-    if ((st = w.abc.ensure(nn * sizeof(float4))) != AORESP_OK) return st;
-    if ((st = w.colp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = w.rowp.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = w.geo.ensure(nn * sizeof(int4))) != AORESP_OK) return st;
-    if ((st = w.grid.ensure(plan.grid_cells * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.fine.ensure(plan.fine_cells * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.hist.ensure((plan.hist_cells + plan.fhist_cells) * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.keys.ensure((size_t)plan.nres * 8)) != AORESP_OK) return st;
+    for (int i = 0; i < kPlanBuffers; ++i)
+        if ((st = need[i].buf->ensure(need[i].bytes)) != AORESP_OK) return st;
     const OutLayout ol(plan.nres);
-    if ((st = w.out.ensure(ol.bytes)) != AORESP_OK) return st;
-    if ((st = w.icount.ensure((size_t)plan.nres * kCountSlots * 4)) != AORESP_OK) return st;
-    if ((st = w.lsum.ensure((plan.corr_items.size() + 1) * kLsWords * sizeof(double))) != AORESP_OK) return st;
-    if ((st = w.srec.ensure(plan.sample_recs * kSampleRec * 4 + 4)) != AORESP_OK) return st;
-    if ((st = w.spart.ensure(plan.sample_part * 4 + 4)) != AORESP_OK) return st;
     if ((st = w.h_out.ensure(ol.bytes)) != AORESP_OK) return st;
-    const size_t total = plan_blob_bytes(plan);
-    if ((st = w.plan.ensure(total)) != AORESP_OK) return st;
-    if ((st = w.h_plan.ensure(total)) != AORESP_OK) return st;
+    if ((st = w.h_plan.ensure(plan_blob_bytes(plan))) != AORESP_OK) return st;
     return AORESP_OK;
 }
 
@@ -605,7 +652,7 @@ void release_workspace(Workspace& w) {
     w.gexec = nullptr;
     if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
     w.cap_stream = nullptr;
-    DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.out,
+    DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.lmax, &w.out,
                       &w.icount, &w.lsum, &w.srec, &w.spart, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
     HostBuf* hb[] = {&w.h_plan, &w.h_out};
@@ -680,7 +727,8 @@ static aoresp_status solve_host_common(const float* P, const float* Q, size_t n,
     if (!ctx) return AORESP_EDEVICE;
     std::lock_guard<std::mutex> lk(ctx->mu);
     Workspace& w = ctx->ws;
-    hipStream_t s = w.stream;
+    hipStream_t s = internal_stream(ctx);
+    if (!s) return AORESP_EDEVICE;
     if ((st = w.P.ensure(3 * n * sizeof(float))) != AORESP_OK) return st;
     if ((st = w.Q.ensure(3 * n * sizeof(float))) != AORESP_OK) return st;
     if (masks && (st = w.masks.ensure(n * k)) != AORESP_OK) return st;

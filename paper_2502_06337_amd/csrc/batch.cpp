@@ -44,7 +44,8 @@ static aoresp_status batch_common(const float* P, const float* Q, const uint64_t
     const float* dQ = Q;
     uint8_t* dM = masks;
     if (host) {
-        s = w.stream;
+        s = internal_stream(ctx);
+        if (!s) return AORESP_EDEVICE;
         if ((st = w.P.ensure(3 * N * sizeof(float) + 4)) != AORESP_OK) return st;
         if ((st = w.Q.ensure(3 * N * sizeof(float) + 4)) != AORESP_OK) return st;
         if (masks && (st = w.masks.ensure(N + 4)) != AORESP_OK) return st;

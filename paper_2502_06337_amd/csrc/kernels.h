@@ -82,6 +82,7 @@ struct Inst {
     int32_t schunk;       // rule 1: circles per band item
     int64_t ssetup_off;   // rule 1: first circle record
     int64_t spart_off;    // rule 1: u32 offset of its partial tiles (chunks x bands x tile words)
+    int64_t lmax_off;     // npk > 1: u32 offset of its local-maximum bitmap (G*G bits) in the bitmap arena
 };
 
 struct FineWin {
@@ -124,9 +125,13 @@ void launch_arc_setup(const float* P, const float* Q, int64_t N, const Inst* ins
 // persistent work-groups pulling from *counter (must be zero on entry).
 void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, uint32_t* counter,
                  uint32_t* grid_arena, uint32_t* err, int blocks, hipStream_t s);
-// cell items: int4 (inst, c0, c1, -); one block each.
+// cell items: int4 (inst, c0, c1, -); one block each.  Slots after the first
+// read the local-maximum bitmap of instances with npk > 1, written once by
+// launch_local_max over the same items.
+void launch_local_max(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, uint32_t* lmax,
+                      hipStream_t s);
 void launch_peak(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, const PeakState* st,
-                 int slot, unsigned long long* keys, hipStream_t s);
+                 int slot, const uint32_t* lmax, unsigned long long* keys, hipStream_t s);
 void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* keys, PeakState* st, int slot,
                         hipStream_t s);
 // correspondence items: int4 (inst, i0, i1, -); one block each.  A block

@@ -11,8 +11,11 @@
 //                    alternative coarse accumulator by the literal sampling
 //                    loop of Algorithm 1: per-circle records, LDS band tiles,
 //                    sum of the per-chunk partial tiles
-//   k_peak           argmax (ties to the lowest index), suppression of earlier
-//                    peaks for multi-model estimation (Sec. IV-D)
+//   k_local_max      multi-model estimation (Sec. IV-D): bitmap of the cells
+//                    that are local maxima within the suppression radius
+//   k_peak           argmax (ties to the lowest index); later peaks of a
+//                    multi-model instance must be local maxima and not
+//                    suppressed by an earlier peak
 //   k_fine_vote      refinement accumulator around each peak
 //   k_fine_peak      refined cell, inverse projection to the axis (Eq. (8))
 //   k_angle_hist     signed angle of every pair about the axis, binned
@@ -407,6 +410,29 @@ __device__ __forceinline__ bool suppressed(int G, int rad, int px, int py, int i
     return d2 <= rr;
 }
 
+// Is cell (ix, iy), holding v votes, a local maximum within the integer disk
+// of radius rad: every other cell of the grid in the disk holds fewer votes,
+// or as many at a higher linear index.
+__device__ bool local_max(const uint32_t* __restrict__ a, int G, int rad, int ix, int iy, uint32_t v) {
+    const int y0 = max(0, iy - rad), y1 = min(G - 1, iy + rad);
+    for (int y = y0; y <= y1; ++y) {
+        const int dy = y - iy;
+        const int rem = rad * rad - dy * dy;
+        int dx = (int)sqrtf((float)rem);
+        while (dx * dx > rem) --dx;
+        while ((dx + 1) * (dx + 1) <= rem) ++dx;
+        const int x0 = max(0, ix - dx), x1 = min(G - 1, ix + dx);
+        const uint32_t* row = a + (size_t)y * (size_t)G;
+        for (int x = x0; x <= x1; ++x) {
+            const uint32_t o = row[x];
+            if (o > v) return false;
+            // equal count: the lower linear index wins
+            if (o == v && (y < iy || (y == iy && x < ix))) return false;
+        }
+    }
+    return true;
+}
+
 __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long k) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -430,10 +456,36 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long k
     return b;
 }
 
+// Local-maximum bitmap of cells [c0, c1) of an instance with several peaks:
+// bit c set iff cell c holds a vote and is a local maximum within radius rad.
+// A wave covers 64 consecutive cells (item bounds are multiples of 64), so its
+// ballot is two words of the bitmap.
+__global__ __launch_bounds__(256) void k_local_max(const uint32_t* __restrict__ grid_arena,
+                                                   const Inst* __restrict__ insts, const int4* __restrict__ items,
+                                                   uint32_t* __restrict__ lmax) {
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
+    if (I.npk < 2) return;
+    const uint32_t* a = grid_arena + I.grid_off;
+    const int G = I.G;
+    const int lane = threadIdx.x & 63;
+    for (int c0 = wi.y + (int)(threadIdx.x & ~63u); c0 < wi.z; c0 += blockDim.x) {
+        const int c = c0 + lane;
+        const uint32_t v = a[c];
+        const bool f = v != 0u && local_max(a, G, I.rad, c % G, c / G, v);
+        const unsigned long long m = __ballot(f);
+        if (lane == 0) {
+            uint32_t* out = lmax + I.lmax_off + (c0 >> 5);
+            out[0] = (uint32_t)m;
+            out[1] = (uint32_t)(m >> 32);
+        }
+    }
+}
+
 // Argmax (ties to the lowest index) of cells [c0, c1) of an instance's grid.
 __global__ __launch_bounds__(256) void k_peak(const uint32_t* __restrict__ grid_arena, const Inst* __restrict__ insts,
                                               const int4* __restrict__ items, const PeakState* st, int slot,
-                                              unsigned long long* keys) {
+                                              const uint32_t* __restrict__ lmax, unsigned long long* keys) {
     __shared__ unsigned long long red[4];
     const int4 wi = items[blockIdx.x];
     const Inst& I = insts[wi.x];
@@ -452,7 +504,12 @@ __global__ __launch_bounds__(256) void k_peak(const uint32_t* __restrict__ grid_
             const uint32_t v = vv[u];
             const int c = 4 * c4 + u;
             if (v == 0u) continue;
+            unsigned long long k = ((unsigned long long)v << 32) | (unsigned long long)(~(uint32_t)c);
+            if (k <= best) continue;
             if (slot > 0) {
+                // later peaks: local maxima (the first peak is the global
+                // maximum, which is one) not suppressed by an earlier peak
+                if (!((lmax[I.lmax_off + (c >> 5)] >> (c & 31)) & 1u)) continue;
                 int ix = c % G, iy = c / G;
                 bool sup = false;
                 for (int t = 0; t < slot && !sup; ++t) {
@@ -461,8 +518,7 @@ __global__ __launch_bounds__(256) void k_peak(const uint32_t* __restrict__ grid_
                 }
                 if (sup) continue;
             }
-            unsigned long long k = ((unsigned long long)v << 32) | (unsigned long long)(~(uint32_t)c);
-            best = k > best ? k : best;
+            best = k;
         }
     }
     best = block_max_u64(best, red);
@@ -1639,10 +1695,17 @@ void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems,
                        nitems, counter, grid_arena, err);
 }
 
-void launch_peak(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, const PeakState* st,
-                 int slot, unsigned long long* keys, hipStream_t s) {
+void launch_local_max(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, uint32_t* lmax,
+                      hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_peak, dim3((unsigned)nitems), dim3(256), 0, s, grid_arena, insts, items, st, slot, keys);
+    hipLaunchKernelGGL(k_local_max, dim3((unsigned)nitems), dim3(256), 0, s, grid_arena, insts, items, lmax);
+}
+
+void launch_peak(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, const PeakState* st,
+                 int slot, const uint32_t* lmax, unsigned long long* keys, hipStream_t s) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(k_peak, dim3((unsigned)nitems), dim3(256), 0, s, grid_arena, insts, items, st, slot, lmax,
+                       keys);
 }
 
 void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* keys, PeakState* st, int slot,

@@ -30,23 +30,49 @@ struct AngleTables {
     float* st = nullptr;
 };
 
-// Growable device buffer.
+// Growable device buffer, or (fixed) a view of caller-provided memory whose
+// ensure() never allocates and fails with ENOMEM beyond its size.
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
+    bool fixed = false;
     aoresp_status ensure(size_t need);
     void release();
     template <class T>
     T* as() const { return static_cast<T*>(ptr); }
 };
 
-// Growable pinned host buffer.
+// Growable pinned host buffer, or (fixed) a view of caller-provided host memory.
 struct HostBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
+    bool fixed = false;
     aoresp_status ensure(size_t need);
     template <class T>
     T* as() const { return static_cast<T*>(ptr); }
+};
+
+// Angle tables of B bins (5 B floats: boundary cos, sin; centre angle, cos,
+// sin) and the in-disk cross ranges of a G x G grid (2 G int16), written into
+// host memory.
+void fill_angle_tables(float* h, int B);
+void fill_disk_table(int16_t* h, int G);
+
+// Where build_plan takes its device tables from when not from the per-device
+// caches: an image in host memory at `host`, to be copied by the caller to the
+// device address `dev` before the plan runs (a single-instance plan uses at
+// most 3 angle-table sizes and one disk table).
+struct TableSink {
+    char* host = nullptr;
+    char* dev = nullptr;
+    size_t cap = 0, used = 0;
+    int nangle = 0;
+    int angle_B[4] = {0, 0, 0, 0};
+    AngleTables angle[4];
+    int disk_G = 0;
+    const int16_t* disk = nullptr;
+    const AngleTables* angle_tables(int B);
+    const int16_t* disk_table(int G);
 };
 
 // A plan's outputs in one device buffer (and its pinned mirror), so that one
@@ -68,6 +94,7 @@ struct Workspace {
     DevBuf abc, colp, rowp, geo;    // per global column
     DevBuf grid, fine, hist;        // arenas
     DevBuf keys;                    // per result slot: peak search keys
+    DevBuf lmax;                    // local-maximum bitmaps of instances with several peaks
     DevBuf out;                     // results, peak states, flag and counter (OutLayout)
     DevBuf icount;                  // partial inlier counters (kCountSlots per result slot)
     DevBuf lsum;                    // least-squares sums per correspondence item (kLsWords doubles)
@@ -95,6 +122,7 @@ struct Plan {
     size_t sample_lds = 0;     // LDS of the sampling band pass (0: no instance uses the sampling rule)
     size_t sample_recs = 0;    // circle records of the sampling rule
     size_t sample_part = 0;    // u32 cells of its partial tiles
+    size_t lmax_words = 0;     // local-maximum bitmaps (G*G/32 words per instance with npk > 1)
 };
 
 // Work split of the coarse vote for one (G, n bucket): LDS tile cells and
@@ -120,7 +148,8 @@ struct DeviceCtx {
 
 Tuning tuning_for(DeviceCtx* ctx, int G, int64_t n);
 
-DeviceCtx* device_ctx();            // context of the current HIP device
+DeviceCtx* device_ctx();            // context of the current HIP device (creates no stream)
+hipStream_t internal_stream(DeviceCtx* ctx);   // its stream for host-pointer calls, created on first use
 const AngleTables* angle_tables(DeviceCtx* ctx, int B);
 const int16_t* disk_table(DeviceCtx* ctx, int G);
 
@@ -129,7 +158,7 @@ aoresp_status build_plan(DeviceCtx* ctx, const int64_t* off, int ninst, const Re
                          Plan& plan);
 // The same with the coarse-vote work split forced (autotuner candidates).
 aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rp, const int* npk,
-                              const Tuning* force, Plan& plan);
+                              const Tuning* force, Plan& plan, TableSink* tables = nullptr);
 // Single solve on device pointers with optional stage events (kNumStages + 1).
 aoresp_status solve_dev_common(const float* P, const float* Q, size_t n, uint32_t k, const aoresp_params* prm,
                                aoresp_result* out, uint8_t* masks, uint32_t* k_found, uint32_t* grid_out,
@@ -156,6 +185,14 @@ aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, st
 void release_workspace(Workspace& w);
 // Allocation half of enqueue_plan + fetch_plan; size of the uploaded blob.
 aoresp_status reserve_plan(Workspace& w, const Plan& plan);
+// The device buffers of reserve_plan with the bytes each needs for `plan`
+// (kPlanBuffers entries, in a fixed order).
+constexpr int kPlanBuffers = 15;
+struct BufNeed {
+    DevBuf* buf;
+    size_t bytes;
+};
+void plan_buffers(Workspace& w, const Plan& plan, BufNeed* out);
 size_t plan_blob_bytes(const Plan& plan);
 // enqueue_plan + fetch_plan captured into one hipGraph and launched on s
 // (caller holds ctx->mu; no stage marks or debug copies).

@@ -210,6 +210,91 @@ def test_topk_with_refinement_parity(aor, orc):
         assert np.array_equal(masks[t], b["mask"])
 
 
+@pytest.mark.parametrize("G,n,target", [(512, 12000, 2e4), (1024, 4000, 1e4), (2048, 2500, 1e4)])
+def test_many_items_per_band_whole_grid(aor, orc, tmp_path, G, n, target):
+    """The coarse vote with a small votes-per-item target forced through the
+    tuner table, so that every band of every pass is split over several work
+    items that flush into the same cells, on varied curves (90% outliers):
+    the whole grid equals the oracle's, bit for bit, and equals the grid of
+    the default split."""
+    import json
+    import _oracle_par
+    inst = synth.make_instance(n, 7000 + G, outlier_rate=0.9)
+    P, Q = dev(inst.P), dev(inst.Q)
+    prm = aor.SolveParams(grid=G, angle_bins=360)
+    aor.tuner_clear()
+    g_default = gpu_grid(aor, inst.P, inst.Q, G).ravel()
+    aor.autotune(P, Q, prm)
+    path = str(tmp_path / "split.jsonl")
+    aor.tuner_save(path)
+    d = json.loads(open(path).read().splitlines()[0])
+    d["tile_cells"], d["vote_target"] = 65536, target
+    with open(path, "w") as f:
+        f.write(json.dumps(d) + "\n")
+    aor.tuner_clear()
+    aor.tuner_load(path)
+    assert aor.tuner_get(G, n)["vote_target"] == pytest.approx(target)
+    g_split = gpu_grid(aor, inst.P, inst.Q, G).ravel()
+    aor.tuner_clear()
+    ref = _oracle_par.coarse_grid(orc, inst.P, inst.Q, G).ravel()
+    assert np.array_equal(g_split, ref), np.flatnonzero(g_split != ref)[:20]
+    assert np.array_equal(g_default, ref)
+
+
+def _broad_and_rim_instance(G, n=20000, seed=77):
+    """Three rotations: a strong one with noisy inliers (sigma = 0.04) whose
+    peak spreads past 5 cells at G = 128, and two weaker ones, one with its axis
+    2.5 cells from the disk rim (the oracle's pins use the same shape)."""
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(-1, 1, (3, n))
+    Q = rng.uniform(-1, 1, (3, n))
+    h = 2.0 / G
+    spec = [((0.05, -0.1), 1.0, 0.4), ((-0.45, 0.35), -2.0, 0.12), ((1 - 2.5 * h, 0.02), 2.4, 0.12)]
+    perm = rng.permutation(n)
+    st = 0
+    for (u, v), t, frac in spec:
+        s = u * u + v * v
+        a = np.array([2 * u, 2 * v, s - 1]) / (1 + s)
+        K = np.array([[0, -a[2], a[1]], [a[2], 0, -a[0]], [-a[1], a[0], 0]])
+        R = np.eye(3) + math.sin(t) * K + (1 - math.cos(t)) * (K @ K)
+        cnt = int(frac * n)
+        idx = perm[st:st + cnt]
+        st += cnt
+        Q[:, idx] = R @ P[:, idx] + 0.04 * rng.standard_normal((3, cnt))
+    return P.astype(np.float32), Q.astype(np.float32)
+
+
+def test_topk_local_maxima_rim_axis(aor, orc):
+    """Sec. IV-D: a broad peak's flank outvotes a rim axis's peak; the peaks
+    are local maxima within the radius, so the rim axis is the third."""
+    G, B, k = 128, 360, 4
+    P, Q = _broad_and_rim_instance(G)
+    prm = aor.SolveParams(grid=G, angle_bins=B, nms_radius=5)
+    outs, masks, st = aor.est_rotations_topk(dev(P), dev(Q), k, prm)
+    masks = masks.cpu().numpy()
+    ors = orc.solve_topk(P, Q, G=G, B=B, k=k, rad=5)
+    assert len(outs) == len(ors) >= 3
+    for t, (a, b) in enumerate(zip(outs, ors)):
+        assert_result_equal(a, b)
+        assert np.array_equal(masks[t], b["mask"])
+
+
+@pytest.mark.parametrize("rad", [1, 3, 12])
+def test_topk_radius_parity(aor, orc, rad):
+    """Local maxima within radii of 1, 3 and 12 cells (disk rows clipped at the
+    grid edge, ties between equal counts at small n), up to 6 peaks."""
+    inst = synth.make_instance(2500, 400 + rad, n_rot=3, inlier_frac_each=0.1, sigma=0.02)
+    G, B, k = 64 if rad == 12 else 128, 360, 6
+    prm = aor.SolveParams(grid=G, angle_bins=B, nms_radius=rad)
+    outs, masks, st = aor.est_rotations_topk(dev(inst.P), dev(inst.Q), k, prm)
+    masks = masks.cpu().numpy()
+    ors = orc.solve_topk(inst.P, inst.Q, G=G, B=B, k=k, rad=rad)
+    assert len(outs) == len(ors)
+    for t, (a, b) in enumerate(zip(outs, ors)):
+        assert_result_equal(a, b)
+        assert np.array_equal(masks[t], b["mask"])
+
+
 def test_enodata(aor):
     P = np.zeros((3, 1), dtype=np.float32)
     r, m, st = aor.est_rotation(P, P, aor.SolveParams(grid=64))

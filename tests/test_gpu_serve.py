@@ -2,7 +2,7 @@
 
 Requests of mixed size submitted from several threads at staggered times
 are admitted while others run; each result must be bit-identical to the
-same problem solved alone with est_rotation.
+same problem solved alone with est_rotation and to the CPU oracle's solve.
 """
 import threading
 import time
@@ -32,7 +32,30 @@ def same(a, b):
     return np.array_equal(a["R"].view(np.uint32), b["R"].view(np.uint32))
 
 
-def test_served_results_equal_solo(aor):
+def matches_oracle(r, o):
+    for k in ("peak_cell", "axis_votes", "fine_cell", "fine_votes", "angle_bin", "angle_votes", "n_inliers",
+              "grid"):
+        if int(r[k]) != int(o[k]):
+            return False
+    return (np.array_equal(np.asarray(r["axis"], np.float32).view(np.uint32), o["axis"].view(np.uint32))
+            and np.array_equal(r["R"].view(np.uint32), o["R"].view(np.uint32)))
+
+
+def oracle_solutions(orc, aor, probs, G=None, B=360, M=16):
+    """The oracle's solve of every problem (threads: the oracle's C code runs
+    without the interpreter lock), with the grid the library picks for n."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(p):
+        if p.n < 2:
+            return None
+        return orc.solve(p.P, p.Q, G=G or aor.grid_for_n(p.n), B=B, M=M)
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        return list(ex.map(one, probs))
+
+
+def test_served_results_equal_solo(aor, orc):
     rng = np.random.default_rng(3)
     sizes = [int(x) for x in np.exp(rng.uniform(np.log(300), np.log(30000), 40))] + [0, 1, 5]
     probs = [synth.make_instance(n, 9000 + t, outlier_rate=0.85) for t, n in enumerate(sizes)]
@@ -67,6 +90,14 @@ def test_served_results_equal_solo(aor):
         assert st == st1
         assert same(res, r1), t
         assert np.array_equal(mask, m1)
+    # and every served result is the oracle's, bit for bit
+    refs = oracle_solutions(orc, aor, probs)
+    for t, p in enumerate(probs):
+        if p.n < 2:
+            continue
+        st, res, mask = served[t]
+        assert matches_oracle(res, refs[t]), (t, p.n)
+        assert np.array_equal(mask, refs[t]["mask"]), t
 
 
 def test_request_larger_than_budget_rejected(aor):
