@@ -106,6 +106,25 @@ aoresp_status est_rotation(const float* P, const float* Q, size_t n, const aores
 aoresp_status est_rotation_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
                                aoresp_result* out, uint8_t* inlier_mask, void* hip_stream);
 
+/* est_rotation_dev without any allocation, for callers that cannot allocate
+ * device memory (code near graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as est_rotation_dev, bit for
+ * bit.  Every device buffer of the solve (tables, 64 B of records per
+ * correspondence, the grid and the refinement, histogram and result arenas)
+ * is carved from one static device array of 96 MiB that each GPU the library
+ * runs on holds until the process ends; host staging comes from one static
+ * host array of 8 MiB.  It calls no hipMalloc, hipFree or hipHostMalloc (the
+ * plan itself is built in ordinary host memory).  A solve that does not fit
+ * (about n = 1.2e6 at G = 1024; the literal sampling rule's partial tiles
+ * at paper scale) returns ENOMEM and runs nothing.  Calls are serialised
+ * inside the process and return after the stream has been synchronised, so
+ * the array is never shared by two solves at a time; every accumulator in it
+ * is cleared by the solve's first kernel, and records are written before
+ * they are read.  Work a caller leaves running on another stream against an
+ * earlier call's outputs is unaffected: outputs live in caller memory. */
+aoresp_status est_rotation_noalloc_dev(const float* P, const float* Q, size_t n, const aoresp_params* prm,
+                                       aoresp_result* out, uint8_t* inlier_mask, void* hip_stream);
+
 /* Several rotations (Sec. IV-D): the peaks are the accumulator's local maxima
  * within an integer disk of nms_radius cells (every other cell of the disk
  * holds fewer votes, or as many at a higher index), taken by decreasing votes

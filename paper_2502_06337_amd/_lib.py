@@ -74,6 +74,8 @@ SIGNATURES = {
     "aoresp_grid_for_n": (C.c_uint32, [C.c_uint64]),
     "est_rotation": (C.c_int, [_fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(Result), _u8p]),
     "est_rotation_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(Result), _u8p, _vp]),
+    "est_rotation_noalloc_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.POINTER(Params), C.POINTER(Result), _u8p,
+                                           _vp]),
     "est_rotations_topk": (C.c_int, [_fp, _fp, C.c_size_t, C.c_uint32, C.POINTER(Params), C.POINTER(Result),
                                      _u8p, C.POINTER(C.c_uint32)]),
     "est_rotations_topk_dev": (C.c_int, [_fp, _fp, C.c_size_t, C.c_uint32, C.POINTER(Params),

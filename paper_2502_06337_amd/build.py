@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libaoresp.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "api.cpp", "batch.cpp", "server.cpp", "tuner.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "batch.cpp", "server.cpp", "tuner.cpp", "noalloc.cpp"]
 ARCH = os.environ.get("AORESP_ARCH", "gfx950")
 
 FLAGS = [
