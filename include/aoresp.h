@@ -200,18 +200,26 @@ aoresp_status aoresp_tuner_clear(void);
 
 /* Request loop: continuous batching of solves under a device-memory budget.
  * aoresp_submit copies the inputs and returns at once; requests that arrive
- * while others run are admitted as memory and slots free up and run in the
- * next batched step.  Results equal est_rotation on the same inputs.        */
+ * while others run are admitted in arrival order as memory and slots free up
+ * and run in the next batched step (two steps can be in flight).  Results
+ * equal est_rotation on the same inputs.  The budget bounds what the loop
+ * holds on the device: both pipelines' cached workspaces and batch arrays,
+ * not only the requests in flight (the library's small per-device angle and
+ * disk tables are outside it).  A request whose deadline passes while it
+ * waits, or before its step finishes, completes with ETIMEDOUT; a step the
+ * device fails completes its requests with EDEVICE; a step whose buffers
+ * cannot be allocated is retried once at the exact size, else ENOMEM.    */
 typedef struct aoresp_server aoresp_server;
 typedef struct {
-    size_t hbm_budget_bytes;  /* device bytes for admitted requests; 0 -> 8 GiB */
+    size_t hbm_budget_bytes;  /* device bytes the loop may hold; 0 -> 8 GiB */
     uint32_t max_slots;       /* requests in one batched step; 0 -> 256 */
     uint32_t timeout_us;      /* per-request deadline from submit; 0 = none */
 } aoresp_server_cfg;
 
 aoresp_status aoresp_server_create(const aoresp_server_cfg* cfg, aoresp_server** out);
-/* P, Q: host (3, n) float32, copied.  ENOMEM if the request alone exceeds the
- * budget.  *req_id identifies the request for aoresp_poll. */
+/* P, Q: host (3, n) float32, copied.  ENOMEM if the request alone, in buffers
+ * sized exactly for it, exceeds the budget.  *req_id identifies the request
+ * for aoresp_poll.  EINVAL once the server is being destroyed. */
 aoresp_status aoresp_submit(aoresp_server* s, const float* P, const float* Q, size_t n, const aoresp_params* prm,
                             uint64_t* req_id);
 /* timeout_us: 0 = do not wait, < 0 = wait until done.  EBUSY if not done.

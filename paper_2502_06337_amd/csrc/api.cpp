@@ -70,7 +70,7 @@ aoresp_status DevBuf::ensure(size_t need) {
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
-    size_t want = need + need / 4 + 256;
+    size_t want = tight ? (need + 255) / 256 * 256 : need + need / 4 + 256;
     if (hipMalloc(&ptr, want) != hipSuccess) {
         ptr = nullptr;
         (void)hipGetLastError();
@@ -652,11 +652,16 @@ void release_workspace(Workspace& w) {
     w.gexec = nullptr;
     if (w.cap_stream) (void)hipStreamDestroy(w.cap_stream);
     w.cap_stream = nullptr;
+    release_workspace_buffers(w);
+}
+
+void release_workspace_buffers(Workspace& w) {
     DevBuf* bufs[] = {&w.abc, &w.colp, &w.rowp, &w.geo, &w.grid, &w.fine, &w.hist, &w.keys, &w.lmax, &w.out,
                       &w.icount, &w.lsum, &w.srec, &w.spart, &w.plan, &w.P, &w.Q, &w.masks};
     for (DevBuf* b : bufs) b->release();
     HostBuf* hb[] = {&w.h_plan, &w.h_out};
     for (HostBuf* b : hb) {
+        if (b->fixed) continue;
         if (b->ptr) (void)hipHostFree(b->ptr);
         b->ptr = nullptr;
         b->bytes = 0;

@@ -36,6 +36,7 @@ struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
     bool fixed = false;
+    bool tight = false;   // grow to the need exactly (else with a quarter of headroom)
     aoresp_status ensure(size_t need);
     void release();
     template <class T>
@@ -183,6 +184,7 @@ aoresp_status collect_plan(Workspace& w, const Plan& plan, aoresp_result* out, s
 aoresp_status finish_plan(Workspace& w, const Plan& plan, aoresp_result* out, std::vector<int>& valid,
                           hipStream_t s);
 void release_workspace(Workspace& w);
+void release_workspace_buffers(Workspace& w);   // device and pinned buffers only
 // Allocation half of enqueue_plan + fetch_plan; size of the uploaded blob.
 aoresp_status reserve_plan(Workspace& w, const Plan& plan);
 // The device buffers of reserve_plan with the bytes each needs for `plan`
