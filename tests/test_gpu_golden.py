@@ -1,0 +1,91 @@
+"""Paper-scale parity against stored oracle outputs (tests/golden/, written by
+tests/golden/make_goldens.py from the CPU oracle only).
+
+The benchmark's launch (n = 10^6, 90% outliers, G = 1024, 64 x 64
+refinement, 3600 angle bins) is compared whole: every row of the coarse
+accumulator by digest, its vote total, the refinement grid row by row, the
+angle histogram, and the result bit for bit, under the default work split and
+under the split the autotuner picks (as the benchmark does).
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2502_06337_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def aor():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2502_06337_amd as aor
+    aor.load_library()
+    return aor
+
+
+def digest(a) -> str:
+    return hashlib.sha256(np.ascontiguousarray(a, dtype="<u4").tobytes()).hexdigest()[:16]
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def make_input(wl):
+    if wl["n_rot"] == 1:
+        return synth.make_instance(wl["n"], wl["seed"], outlier_rate=wl["outlier_rate"], sigma=0.01)
+    return synth.make_instance(wl["n"], wl["seed"], n_rot=wl["n_rot"], inlier_frac_each=0.1, sigma=0.01)
+
+
+def assert_grid_rows(grid, rows, total):
+    grid = np.asarray(grid).view(np.uint32)
+    got = [digest(r) for r in grid]
+    bad = [i for i, (a, b) in enumerate(zip(got, rows)) if a != b]
+    assert len(got) == len(rows) and not bad, f"rows differing from the oracle: {bad[:20]} ({len(bad)} in all)"
+    assert int(grid.astype(np.uint64).sum()) == total
+
+
+def assert_result(r, g, mask=None):
+    for k in ("peak_cell", "axis_votes", "fine_cell", "fine_votes", "angle_bin", "angle_votes", "n_inliers", "grid"):
+        assert int(r[k]) == g[k], (k, r[k], g[k])
+    assert [int(x) for x in np.asarray(r["axis"], np.float32).view(np.uint32)] == g["axis_bits"]
+    assert int(np.float32(r["angle"]).view(np.uint32)) == g["angle_bits"]
+    assert [int(x) for x in np.asarray(r["R"], np.float32).ravel().view(np.uint32)] == g["R_bits"]
+    if mask is not None:
+        assert hashlib.sha256(np.ascontiguousarray(mask, np.uint8).tobytes()).hexdigest()[:16] == g["mask_sha256"]
+
+
+@pytest.mark.parametrize("tuned", [False, True], ids=["default_split", "tuned_split"])
+def test_paper_scale_solve_whole(aor, tuned):
+    gold = load("c2_seed2000.json")
+    wl = gold["params"]
+    inst = make_input(wl)
+    P = torch.from_numpy(inst.P).cuda()
+    Q = torch.from_numpy(inst.Q).cuda()
+    prm = aor.SolveParams(grid=wl["G"], refine_grid=wl["M"], refine_halfwin=wl["w"], angle_bins=wl["B"],
+                          inlier_thresh=wl["tau"])
+    aor.tuner_clear()
+    if tuned:
+        aor.autotune(P, Q, prm)
+    out = aor.solve_debug(P, Q, prm)
+    torch.cuda.synchronize()
+    assert_grid_rows(out["grid"].cpu().numpy(), gold["coarse_rows"], gold["coarse_sum"])
+    g = gold["results"][0]
+    fine = out["fine"].cpu().numpy().view(np.uint32)
+    assert [digest(r) for r in fine] == g["fine_rows"]
+    assert digest(out["hist"].cpu().numpy().view(np.uint32)) == g["hist_sha256"]
+    assert_result(out["result"], g, out["mask"].cpu().numpy())
+    # the entry point the benchmark times returns the same result and mask
+    r, m, st = aor.est_rotation(P, Q, prm)
+    assert st == 0
+    assert_result(r, g, m.cpu().numpy())
+    aor.tuner_clear()
