@@ -96,7 +96,13 @@ typedef struct {
 } aoresp_result;
 
 /* Grid resolution chosen for n when params.grid == 0: a pure function of n
- * (so batched, served and one-at-a-time solves agree). */
+ * (so batched, served and one-at-a-time solves agree), looked up by
+ * floor(log2 n) in a table the library is built with.  The table comes from
+ * an offline sweep (paper_2502_06337_amd/tune_grid.py) of rotation error and
+ * solve time at G = 128..1024 on seeded problems shaped like the batched
+ * workload: the smallest G whose mean error (capped at 5 degrees) is within a
+ * factor 1.25 of the best, non-decreasing in n.  Its scores and version are in
+ * paper_2502_06337_amd/grid_table.json. */
 uint32_t aoresp_grid_for_n(uint64_t n);
 
 /* Single rotation (Sec. I; Algorithm 1).  P, Q: host (3, n) float32.

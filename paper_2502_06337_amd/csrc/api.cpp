@@ -13,6 +13,10 @@
 #include "runtime.h"
 
 namespace aoresp {
+#include "grid_table.inc"
+}
+
+namespace aoresp {
 
 // Set AORESP_DEBUG=1 to print the HIP error behind an AORESP_EDEVICE.
 static bool debug_on() {
@@ -422,6 +426,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
         if (marks) (void)hipEventRecord(marks[k], s);
     };
     if ((st = reserve_plan(w, plan)) != AORESP_OK) return st;
+    ++w.gen;
     const OutLayout ol(plan.nres);
     // instance table and work items, uploaded as one blob
     const size_t b_inst = (size_t)ninst * sizeof(Inst);
@@ -767,10 +772,16 @@ using namespace aoresp;
 extern "C" {
 
 uint32_t aoresp_grid_for_n(uint64_t n) {
-    if (n < 2000) return 128;
-    if (n < 20000) return 256;
-    if (n < 200000) return 512;
-    return 1024;
+    // the autotuned table, by size bucket floor(log2 n)
+    int b = 0;
+    while (n >= 2) {
+        n >>= 1;
+        ++b;
+    }
+    int i = b - kGridTableFirst;
+    const int last = (int)(sizeof(kGridTable) / sizeof(kGridTable[0])) - 1;
+    i = i < 0 ? 0 : (i > last ? last : i);
+    return (uint32_t)kGridTable[i];
 }
 
 aoresp_status est_rotation(const float* P, const float* Q, size_t n, const aoresp_params* prm, aoresp_result* out,

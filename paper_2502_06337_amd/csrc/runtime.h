@@ -90,24 +90,6 @@ struct OutLayout {
     }
 };
 
-// Everything a batch enqueues into.
-struct Workspace {
-    DevBuf abc, colp, rowp, geo;    // per global column
-    DevBuf grid, fine, hist;        // arenas
-    DevBuf keys;                    // per result slot: peak search keys
-    DevBuf lmax;                    // local-maximum bitmaps of instances with several peaks
-    DevBuf out;                     // results, peak states, flag and counter (OutLayout)
-    DevBuf icount;                  // partial inlier counters (kCountSlots per result slot)
-    DevBuf lsum;                    // least-squares sums per correspondence item (kLsWords doubles)
-    DevBuf srec, spart;             // sampling rule: circle records, partial band tiles
-    DevBuf plan;                    // instance table + work items
-    DevBuf P, Q, masks;             // staging for host-pointer entry points
-    HostBuf h_plan, h_out;          // pinned mirrors
-    hipStream_t stream = nullptr;   // internal stream for host-pointer calls
-    hipStream_t cap_stream = nullptr;   // stream that batched plans are captured on
-    hipGraphExec_t gexec = nullptr;     // last captured plan, updated in place when the topology repeats
-};
-
 // A batch laid out for the kernels.
 struct Plan {
     std::vector<Inst> insts;
@@ -125,6 +107,34 @@ struct Plan {
     size_t sample_part = 0;    // u32 cells of its partial tiles
     size_t lmax_words = 0;     // local-maximum bitmaps (G*G/32 words per instance with npk > 1)
 };
+
+// Everything a batch enqueues into.
+struct Workspace {
+    DevBuf abc, colp, rowp, geo;    // per global column
+    DevBuf grid, fine, hist;        // arenas
+    DevBuf keys;                    // per result slot: peak search keys
+    DevBuf lmax;                    // local-maximum bitmaps of instances with several peaks
+    DevBuf out;                     // results, peak states, flag and counter (OutLayout)
+    DevBuf icount;                  // partial inlier counters (kCountSlots per result slot)
+    DevBuf lsum;                    // least-squares sums per correspondence item (kLsWords doubles)
+    DevBuf srec, spart;             // sampling rule: circle records, partial band tiles
+    DevBuf plan;                    // instance table + work items
+    DevBuf P, Q, masks;             // staging for host-pointer entry points
+    HostBuf h_plan, h_out;          // pinned mirrors
+    hipStream_t stream = nullptr;   // internal stream for host-pointer calls
+    hipStream_t cap_stream = nullptr;   // stream that batched plans are captured on
+    hipGraphExec_t gexec = nullptr;     // last captured plan, updated in place when the topology repeats
+    uint64_t gen = 0;                   // bumped by every enqueue_plan into this workspace
+    // A batched call kept for replay: the key it was recorded for (offsets,
+    // resolved parameters, work splits, device pointers), the workspace
+    // generation right after recording, and its plan.  A later call with the
+    // same key and no other use of the workspace in between launches gexec
+    // again without planning or capturing.
+    std::vector<uint64_t> replay_key;
+    uint64_t replay_gen = 0;
+    Plan replay_plan;
+};
+
 
 // Work split of the coarse vote for one (G, n bucket): LDS tile cells and
 // votes per work item.  Any choice gives the same grid; only speed differs.

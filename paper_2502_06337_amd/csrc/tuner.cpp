@@ -2,8 +2,9 @@
 // the coarse-vote stage of one solve on the caller's data under each
 // candidate (LDS tile size x votes per work item), keeps the fastest in the
 // per-device table that build_plan consults, and can save and load that
-// table as JSON lines.  The grid resolution is not tuned: G stays the pure
-// function aoresp_grid_for_n(n) (or the caller's choice), so results never
+// table as JSON lines.  The grid resolution is not tuned here, at run time:
+// G is the caller's choice or aoresp_grid_for_n(n), a table fixed when the
+// library is built (from the offline sweep of tune_grid.py), so results never
 // depend on tuning, batch composition or machine.
 #include <hip/hip_runtime.h>
 

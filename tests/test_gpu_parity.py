@@ -359,6 +359,38 @@ def test_batch_graph_relaunched_with_changing_batches(aor):
             assert np.array_equal(mask[off[t]:off[t + 1]], m1), (rep, t)
 
 
+def test_batch_graph_replayed_on_new_data(aor):
+    """A batched call with the same layout as the previous one (offsets,
+    parameters, device pointers) launches the recorded graph again: with the
+    inputs overwritten in place between calls, and with a single solve in
+    between (which forces a new recording), every result equals the
+    one-at-a-time solve of the current data."""
+    sizes = [2000, 500, 3000, 64]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    prm = aor.SolveParams(angle_bins=360, refine_grid=16)
+    Pd = torch.zeros((3, int(off[-1])), dtype=torch.float32, device="cuda")
+    Qd = torch.zeros_like(Pd)
+    for rep, single_between in enumerate([False, False, True, False, False]):
+        insts = [synth.make_instance(n, 8100 + 10 * rep + t, outlier_rate=0.85) for t, n in enumerate(sizes)]
+        Pd.copy_(torch.from_numpy(np.concatenate([i.P for i in insts], axis=1)))
+        Qd.copy_(torch.from_numpy(np.concatenate([i.Q for i in insts], axis=1)))
+        if single_between:
+            aor.est_rotation(insts[0].P, insts[0].Q, prm)
+        outs, _, _ = aor.est_rotation_batch(Pd, Qd, off, prm, want_mask=False)
+        torch.cuda.synchronize()
+        for t in range(len(sizes)):
+            r1, _, _ = aor.est_rotation(insts[t].P, insts[t].Q, prm)
+            assert_result_equal(outs[t], r1)
+        # the solo solves above used the workspace: the next call records again,
+        # and the one after it replays
+        outs2, _, _ = aor.est_rotation_batch(Pd, Qd, off, prm, want_mask=False)
+        outs3, _, _ = aor.est_rotation_batch(Pd, Qd, off, prm, want_mask=False)
+        torch.cuda.synchronize()
+        for t in range(len(sizes)):
+            assert_result_equal(outs2[t], outs[t])
+            assert_result_equal(outs3[t], outs[t])
+
+
 # ------------------------------------------------------ full size, sampled
 def test_paper_scale_sampled_parity(aor, orc):
     """n = 1e6, G = 1024 + 64x64 refinement, B = 3600 (the benchmark's launch
