@@ -265,7 +265,9 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
     auto angle_of = [ctx, tables](int B) { return tables ? tables->angle_tables(B) : angle_tables(ctx, B); };
     plan = Plan();
     plan.insts.resize(ninst);
-    std::vector<std::pair<double, int4>> votes, samples;
+    std::vector<std::pair<double, int4>> samples;
+    // coarse-vote items grouped by chunk of correspondences: (weight, item)
+    std::vector<std::vector<std::pair<double, int4>>> chunks;
     size_t hist_lds = 0;
     for (int b = 0; b < ninst; ++b) {
         const ResolvedParams& rp = rps[b];
@@ -368,16 +370,19 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
                     samples.push_back({share * (double)(i1 - i0), make_int4(b, band, (int)i0, (int)i1)});
                 }
         }
-        for (int mode = 0; mode < 2 && rp.rule == 0; ++mode)
-            for (int band = 0; band < nbands; ++band)
-                for (int64_t i0 = 0; i0 < n; i0 += chunk) {
-                    int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
-                    // central bands carry more votes: weight by the band's in-disk share
-                    double c = (band + 0.5) * bw / (double)rp.G * 2.0 - 1.0;
-                    double share = std::sqrt(std::max(0.05, 1.0 - c * c));
-                    votes.push_back({per_arc * (double)(i1 - i0) * share,
-                                     make_int4(b, mode | (band << 1), (int)i0, (int)i1)});
-                }
+        if (rp.rule == 0)
+            for (int64_t i0 = 0; i0 < n; i0 += chunk) {
+                int64_t i1 = i0 + chunk < n ? i0 + chunk : n;
+                chunks.emplace_back();
+                for (int mode = 0; mode < 2; ++mode)
+                    for (int band = 0; band < nbands; ++band) {
+                        // central bands carry more votes: weight by the band's in-disk share
+                        double c = (band + 0.5) * bw / (double)rp.G * 2.0 - 1.0;
+                        double share = std::sqrt(std::max(0.05, 1.0 - c * c));
+                        chunks.back().push_back({per_arc * (double)(i1 - i0) * share,
+                                                 make_int4(b, mode | (band << 1), (int)i0, (int)i1)});
+                    }
+            }
         for (int64_t c0 = 0; c0 < (int64_t)rp.G * rp.G; c0 += kCellChunk) {
             int64_t c1 = c0 + kCellChunk < (int64_t)rp.G * rp.G ? c0 + kCellChunk : (int64_t)rp.G * rp.G;
             plan.cell_items.push_back(make_int4(b, (int)c0, (int)c1, 0));
@@ -394,10 +399,36 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
             }
     }
     for (Inst& I : plan.insts) I.fhist_off += (int64_t)plan.hist_cells;
-    std::stable_sort(votes.begin(), votes.end(),
-                     [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
-    plan.vote_items.reserve(votes.size());
-    for (auto& v : votes) plan.vote_items.push_back(v.second);
+    // Coarse-vote queues, one per XCD: chunks (largest first) go to the
+    // least-loaded queue; a queue lists its chunks one after the other, each
+    // chunk's band items largest first, so that the work-groups of an XCD
+    // take the bands of the same correspondences at the same time.
+    auto heavier = [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; };
+    std::vector<std::pair<double, int>> order;
+    for (size_t c = 0; c < chunks.size(); ++c) {
+        std::stable_sort(chunks[c].begin(), chunks[c].end(), heavier);
+        double wsum = 0.0;
+        for (auto& v : chunks[c]) wsum += v.first;
+        order.push_back({wsum, (int)c});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const std::pair<double, int>& x, const std::pair<double, int>& y) { return x.first > y.first; });
+    std::vector<int> queue_of(chunks.size(), 0);
+    double load[kVoteQueues] = {};
+    for (auto& o : order) {
+        int q = 0;
+        for (int k = 1; k < kVoteQueues; ++k)
+            if (load[k] < load[q]) q = k;
+        queue_of[o.second] = q;
+        load[q] += o.first;
+    }
+    for (int q = 0; q < kVoteQueues; ++q) {
+        plan.vote_q.first[q] = (int32_t)plan.vote_items.size();
+        for (auto& o : order)
+            if (queue_of[o.second] == q)
+                for (auto& v : chunks[o.second]) plan.vote_items.push_back(v.second);
+    }
+    plan.vote_q.first[kVoteQueues] = (int32_t)plan.vote_items.size();
     std::stable_sort(samples.begin(), samples.end(),
                      [](const std::pair<double, int4>& x, const std::pair<double, int4>& y) { return x.first > y.first; });
     for (auto& v : samples) plan.sample_items.push_back(v.second);
@@ -467,7 +498,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     aoresp_result* res = reinterpret_cast<aoresp_result*>(ob + ol.o_res);
     unsigned long long* keys = w.keys.as<unsigned long long>();
     uint32_t* err = reinterpret_cast<uint32_t*>(ob + ol.o_err);
-    uint32_t* counter = err + 1;
+    uint32_t* counters = err + 1;   // kVoteQueues of them, zeroed with the out region
 
     mark(0);
     // every accumulator and flag of the plan starts at zero: one launch
@@ -486,7 +517,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     launch_zero_list(zl, s);
     launch_arc_setup(P, Q, N, insts, ninst, R, s);
     mark(1);
-    launch_vote(R, insts, vote_items, (int)plan.vote_items.size(), counter, w.grid.as<uint32_t>(), err,
+    launch_vote(R, insts, vote_items, plan.vote_q, counters, w.grid.as<uint32_t>(), err,
                 ctx->cu_count, s);
     launch_sample_vote(P, Q, N, insts, sample_setup_items, (int)plan.sample_setup_items.size(), sample_items,
                        (int)plan.sample_items.size(), cell_items, (int)plan.cell_items.size(), w.srec.as<uint32_t>(),

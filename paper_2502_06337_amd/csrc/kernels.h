@@ -122,8 +122,16 @@ void launch_zero_list(const ZeroList& zl, hipStream_t s);
 void launch_arc_setup(const float* P, const float* Q, int64_t N, const Inst* insts, int ninst, ArcRecs recs,
                       hipStream_t s);
 // items: int4 (inst, mode | band << 1, i0, i1), processed by `blocks`
-// persistent work-groups pulling from *counter (must be zero on entry).
-void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, uint32_t* counter,
+// persistent work-groups.  The items form kVoteQueues consecutive queues, one
+// per XCD: queue q holds items [first[q], first[q + 1]) and its counter is
+// counters[q] (all zero on entry).  Work-group b runs on XCD b mod 8 (the
+// hardware deals work-groups to the XCDs in turn) and pulls from queue
+// b mod kVoteQueues, then from the others once its own is empty.
+constexpr int kVoteQueues = 8;
+struct VoteQueues {
+    int32_t first[kVoteQueues + 1];
+};
+void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, VoteQueues q, uint32_t* counters,
                  uint32_t* grid_arena, uint32_t* err, int blocks, hipStream_t s);
 // cell items: int4 (inst, c0, c1, -); one block each.  Slots after the first
 // read the local-maximum bitmap of instances with npk > 1, written once by

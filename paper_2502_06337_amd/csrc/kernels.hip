@@ -152,8 +152,8 @@ struct CoarseEmit {
 // block-wide barrier between listing and walking.  At the end the rings are
 // drained, and the tile is flushed (disk mask applied) with global atomics.
 __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const Inst* __restrict__ insts,
-                                                       const int4* __restrict__ items, int nitems,
-                                                       uint32_t* __restrict__ counter,
+                                                       const int4* __restrict__ items, const VoteQueues vq,
+                                                       uint32_t* __restrict__ counters,
                                                        uint32_t* __restrict__ grid_arena,
                                                        uint32_t* __restrict__ err) {
     constexpr int kWaves = kVoteThreads / 64;
@@ -169,14 +169,27 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
     int16_t* dlim = reinterpret_cast<int16_t*>(sinkrow + 64);
     uint32_t bad = 0;
 
+    // the queue of this work-group's XCD first; its chunks' records stay in
+    // that XCD's L2 while the work-groups there take the chunks' bands
+    const int home = (int)(blockIdx.x % kVoteQueues);
+    int q_left = (1 << kVoteQueues) - 1;   // thread 0: queues not yet found empty
     for (;;) {
         if (tid == 0) {
-            item_id = (int)atomicAdd(counter, 1u);
+            int got = -1;
+            for (int k = 0; k < kVoteQueues && got < 0; ++k) {
+                const int q = (home + k) & (kVoteQueues - 1);
+                if (!((q_left >> q) & 1)) continue;
+                const int len = vq.first[q + 1] - vq.first[q];
+                const int t = len > 0 ? (int)atomicAdd(&counters[q], 1u) : len;
+                if (t < len) got = vq.first[q] + t;
+                else q_left &= ~(1 << q);
+            }
+            item_id = got;
             group_next = kWaves * 64;
         }
         __syncthreads();
         const int it = item_id;
-        if (it >= nitems) break;
+        if (it < 0) break;
         const int4 wi = items[it];
         const Inst& I = insts[wi.x];
         const int G = I.G;
@@ -1686,13 +1699,14 @@ void launch_arc_setup(const float* P, const float* Q, int64_t N, const Inst* ins
     hipLaunchKernelGGL(k_arc_setup, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, P, Q, N, insts, ninst, recs);
 }
 
-void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, int nitems, uint32_t* counter,
+void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, VoteQueues q, uint32_t* counters,
                  uint32_t* grid_arena, uint32_t* err, int blocks, hipStream_t s) {
+    const int nitems = q.first[kVoteQueues];
     if (nitems <= 0) return;
     if (blocks > nitems) blocks = nitems;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_vote, dim3((unsigned)blocks), dim3(kVoteThreads), coarse_lds_bytes(), s, recs, insts, items,
-                       nitems, counter, grid_arena, err);
+                       q, counters, grid_arena, err);
 }
 
 void launch_local_max(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, uint32_t* lmax,

@@ -86,7 +86,7 @@ struct OutLayout {
         o_res = 0;
         o_st = up((size_t)nres * sizeof(aoresp_result));
         o_err = o_st + up((size_t)nres * sizeof(PeakState));
-        bytes = o_err + 16;
+        bytes = o_err + 64;   // flag, then the coarse vote's kVoteQueues work counters
     }
 };
 
@@ -94,6 +94,7 @@ struct OutLayout {
 struct Plan {
     std::vector<Inst> insts;
     std::vector<int4> vote_items, cell_items, corr_items, list_items;
+    VoteQueues vote_q;         // vote_items in kVoteQueues consecutive queues
     std::vector<int4> sample_setup_items, sample_items;   // sampling rule: circle records, band items
     int64_t N = 0;
     size_t grid_cells = 0, fine_cells = 0, hist_cells = 0;
