@@ -9,13 +9,18 @@ A step = one full solve (setup, coarse vote, peak, refinement, angle
 histogram, Rodrigues, inlier mask) with P and Q already resident in HBM.
 
 Prints one JSON line: Mcorr/s, the roofline of the dominant kernel (coarse
-vote) measured with HIP events on the launch stream, and the CPU oracle timed
-on a bounded sample of the same workload.  Beside the headline it reports the
-batched workload (256 instances, n log-uniform in [1e3, 1e5]: one batched
-call against a one-at-a-time loop) and a served stream (Poisson arrivals at
-2000 requests/s, n log-uniform in [1e3, 1e6], 90% outliers, 8 GiB budget,
-shortened to --serve-seconds: the request loop against a one-at-a-time loop
-fed the same arrivals).
+vote) measured with HIP events on the launch stream (against the lane-op rate
+without FMA or packed math, against the published fp32 rate, and against the
+LDS-atomic rate measured on the GPU), and the CPU oracle timed on bounded
+samples of the same workload.  Beside the headline it reports: the literal
+sampling rule and coarse-to-fine angle voting on the same input; the
+rotation-error distribution of small solves (n = 1000, 200 seeds) for the GPU
+and the oracle; the multi-rotation workload (n = 1e6, three rotations, top-3);
+the batched workload (256 instances, n log-uniform in [1e3, 1e5]: batched
+calls against a one-at-a-time loop); and a served stream (Poisson arrivals at
+2000 requests/s for --serve-seconds, n log-uniform in [1e3, 1e6], 90%
+outliers, 8 GiB budget: the request loop against a one-at-a-time loop fed
+the same arrivals and a rate it sustains).
 """
 from __future__ import annotations
 
@@ -38,8 +43,10 @@ ALU_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12   # non-packed fp32 lane ops/s: 256 CU
 STAGES = ["setup", "coarse_vote", "peak", "refine", "angle", "inliers"]
 
 
+# the vote kernel's sources and the planner that lays out its work items
 KERNEL_SOURCES = ["paper_2502_06337_amd/csrc/kernels.hip", "paper_2502_06337_amd/csrc/kernels.h",
-                  "paper_2502_06337_amd/csrc/walker.h", "paper_2502_06337_amd/csrc/geometry.h"]
+                  "paper_2502_06337_amd/csrc/walker.h", "paper_2502_06337_amd/csrc/geometry.h",
+                  "paper_2502_06337_amd/csrc/api.cpp"]
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_vote_hbm_traffic_c2.json")
 
 
@@ -84,6 +91,53 @@ def cpu_model() -> str:
     except OSError:
         pass
     return platform.processor() or "unknown"
+
+
+PUBLISHED_FP32_TFLOPS = 157.3   # MI355X vector fp32, FMA and packed counted as published
+
+
+def measured_roofs(cu_count: int) -> dict:
+    """The two roofs of the coarse vote measured on this GPU: conflict-free
+    32-bit LDS atomic adds per second over all CUs, and a streaming device
+    copy (bytes read + written per second)."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_2502_06337_amd", "libaoresp_probe.so")
+    P = C.CDLL(path)
+    P.aoresp_probe_lds_atomics.restype = C.c_double
+    P.aoresp_probe_lds_atomics.argtypes = [C.c_int, C.c_int]
+    P.aoresp_probe_copy.restype = C.c_double
+    P.aoresp_probe_copy.argtypes = [C.c_size_t, C.c_int]
+    lds = max(P.aoresp_probe_lds_atomics(cu_count, 2000) for _ in range(3))
+    copy = max(P.aoresp_probe_copy(1 << 30, 10) for _ in range(2))
+    return {"lds_atomic_per_s": lds, "hbm_copy_GBps": copy / 1e9, "cu_count": cu_count}
+
+
+def bench_c1(aor, synth, torch, seeds: int) -> dict:
+    """Plain solves at n = 1000 (10% inliers, sigma = 0.01), G = 256, 360 angle
+    bins, over `seeds` seeds: rotation error for the GPU path and for the CPU
+    oracle (threads over seeds), and whether each pair of results is the same
+    bit for bit."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle as orc   # the oracle's accuracy beside the GPU's (test infrastructure)
+    orc.lib()
+    insts = [synth.make_instance(1000, synth.config_seed(1, t), outlier_rate=0.9, sigma=0.01) for t in range(seeds)]
+    prm = aor.SolveParams(grid=256, angle_bins=360)
+    gpu = [aor.est_rotation(i.P, i.Q, prm, want_mask=False)[0] for i in insts]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        ref = list(ex.map(lambda i: orc.solve(i.P, i.Q, G=256, B=360), insts))
+    t_or = time.perf_counter() - t0
+    eg = np.array([rotation_error_deg(i.R_gt[0], r["R"]) for i, r in zip(insts, gpu)])
+    eo = np.array([rotation_error_deg(i.R_gt[0], r["R"]) for i, r in zip(insts, ref)])
+    same = sum(int(np.array_equal(a["R"].view(np.uint32), b["R"].view(np.uint32)) and a["peak_cell"] == b["peak_cell"]
+                   and a["angle_bin"] == b["angle_bin"]) for a, b in zip(gpu, ref))
+
+    def dist(e):
+        return {"median": round(float(np.median(e)), 4), "p90": round(float(np.percentile(e, 90)), 4),
+                "max": round(float(e.max()), 4), "over_5deg": int((e > 5.0).sum())}
+    return {"workload": f"n=1000, 90% outliers, sigma=0.01, G=256, B=360, seeds 1000..{999 + seeds}",
+            "rotation_error_deg_gpu": dist(eg), "rotation_error_deg_oracle": dist(eo), "identical": same,
+            "seeds": seeds, "oracle_s": round(t_or, 1)}
 
 
 def bench_c2f(aor, L, C, torch, P, Q, inst, reps: int) -> dict:
@@ -232,7 +286,23 @@ def bench_batch(aor, synth, torch, reps: int) -> dict:
     for o in outs:
         grids[str(int(o["grid"]))] = grids.get(str(int(o["grid"])), 0) + 1
     errs = [rotation_error_deg(i.R_gt[0], o["R"]) for i, o in zip(insts, outs)]
+    # the oracle on the host cores: every instance's first 300 correspondences,
+    # same G and B, one instance per thread
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle as orc   # CPU baseline of the batched workload (a bounded sample)
+    orc.lib()
+    m = 300
+    workers = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(lambda ib: orc.solve(ib[0].P[:, :m].copy(), ib[0].Q[:, :m].copy(), G=int(ib[1]["grid"]), B=360),
+                    zip(insts, outs)))
+    t_or = time.perf_counter() - t0
+    cpu = {"value": 256 * m / t_or / 1e6, "unit": "Mcorr/s", "cores": workers, "kind": "oracle",
+           "sample": f"first {m} correspondences of each of the 256 instances at its G, B=360; brute-force C oracle, "
+                     f"one instance per thread, {t_or:.1f} s"}
     return {"workload": "256 instances, n log-U[1e3,1e5], rho U[0.5,0.95], sigma U[0.001,0.02], B=360",
+            "cpu_baseline": cpu,
             "total_n": total, "grids": grids, "batched_ms": round(bt * 1e3, 3),
             "batched_first_call_ms": round(ft * 1e3, 3), "plain_loop_ms": round(lt * 1e3, 3),
             "speedup": round(lt / bt, 3), "batched_Mcorr_s": round(total / bt / 1e6, 2),
@@ -354,7 +424,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_CORR)
-    ap.add_argument("--cpu-sample", type=int, default=3000,
+    ap.add_argument("--cpu-sample", type=int, default=1500,
                     help="correspondences timed with the CPU oracle (0 = skip)")
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--no-tune", action="store_true", help="skip the work-split autotuner")
@@ -363,6 +433,8 @@ def main() -> int:
     ap.add_argument("--serve-seconds", type=float, default=30.0, help="served stream length (0 = skip)")
     ap.add_argument("--sample-reps", type=int, default=5,
                     help="literal sampling rule repetitions on the headline input (0 = skip)")
+    ap.add_argument("--c1-seeds", type=int, default=200,
+                    help="small plain solves (n = 1000) for the rotation-error distribution, GPU and oracle (0 = skip)")
     ap.add_argument("--c2f-reps", type=int, default=10,
                     help="coarse-to-fine angle voting repetitions on the headline input (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -437,19 +509,28 @@ def main() -> int:
     votes = int(dbg["grid"].to(torch.int64).sum().item())
     t_vote = stage_avg[1] * 1e-3
     achieved = OPS_PER_VOTE * votes / t_vote / 1e12
+    roofs = measured_roofs(torch.cuda.get_device_properties(dev).multi_processor_count)
 
     cpu = None
     if args.cpu_sample > 0:
         m = min(args.cpu_sample, args.n)
-        Ps, Qs = inst.P[:, :m].copy(), inst.Q[:, :m].copy()
         import oracle as orc   # the CPU baseline leg: the oracle timed on a sample
         orc.lib()
-        t1 = time.perf_counter()
-        orc.solve(Ps, Qs, G=G, B=B, M=M, tau=0.05)
-        tc = time.perf_counter() - t1
-        cpu = {"value": m / tc / 1e6, "unit": "Mcorr/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {m} of the {args.n} correspondences, same G={G}, M={M}, B={B}; "
-                         f"single-threaded C oracle, {tc:.1f} s; host {cpu_model()}, nproc {os.cpu_count()}"}
+        rates, secs = [], []
+        for seed in (args.seed, args.seed + 1, args.seed + 2):
+            si = inst if seed == args.seed else synth.make_instance(m, seed, outlier_rate=0.9, sigma=0.01)
+            Ps, Qs = si.P[:, :m].copy(), si.Q[:, :m].copy()
+            t1 = time.perf_counter()
+            orc.solve(Ps, Qs, G=G, B=B, M=M, tau=0.05)
+            tc = time.perf_counter() - t1
+            rates.append(m / tc / 1e6)
+            secs.append(round(tc, 1))
+        cpu = {"value": float(np.mean(rates)), "unit": "Mcorr/s", "cores": 1, "kind": "oracle",
+               "per_seed": [round(r, 7) for r in rates],
+               "sample": f"first {m} correspondences of the headline input (seed {args.seed}) and of seeds "
+                         f"{args.seed + 1}, {args.seed + 2}, same G={G}, M={M}, B={B}; single-threaded C oracle, "
+                         f"a brute-force pass over every cell for every correspondence (O(n G^2)), "
+                         f"{'/'.join(str(x) for x in secs)} s; host {cpu_model()}, nproc {os.cpu_count()}"}
 
     line = {
         "metric": "Mcorr/s at n=1e6, 90% outliers",
@@ -469,13 +550,19 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TFLOPS, 2),
                      "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(),
                      "kernel": "k_vote", "kernel_ms": round(stage_avg[1], 4), "votes": votes,
-                     "ops_per_vote": OPS_PER_VOTE},
+                     "ops_per_vote": OPS_PER_VOTE,
+                     "frac_of_published_fp32": round(achieved / PUBLISHED_FP32_TFLOPS, 4),
+                     "lds_atomic": {"achieved_per_s": votes / t_vote, "peak_measured_per_s": roofs["lds_atomic_per_s"],
+                                    "frac": round(votes / t_vote / roofs["lds_atomic_per_s"], 4)
+                                    if roofs["lds_atomic_per_s"] > 0 else None},
+                     "hbm_copy_GBps_measured": round(roofs["hbm_copy_GBps"], 1)},
         "cpu_baseline": cpu,
         "stages_ms": {k: round(float(v), 4) for k, v in zip(STAGES, stage_avg)},
         "tuning": tuning,
         "sample_rule": bench_sample_rule(aor, L, C, torch, P, Q, inst, args.sample_reps)
         if args.sample_reps > 0 else None,
         "angle_c2f": bench_c2f(aor, L, C, torch, P, Q, inst, args.c2f_reps) if args.c2f_reps > 0 else None,
+        "c1": bench_c1(aor, synth, torch, args.c1_seeds) if args.c1_seeds > 0 else None,
         "topk": bench_topk(aor, synth, torch, args.topk_reps) if args.topk_reps > 0 else None,
         "batch": bench_batch(aor, synth, torch, args.batch_reps) if args.batch_reps > 0 else None,
         "serve": bench_serve(aor, synth, args.serve_seconds) if args.serve_seconds > 0 else None,

@@ -54,6 +54,25 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Device probes the benchmark runs to measure its roofs (a separate small library).
+PROBE_SRC = os.path.join(CSRC, "probe.hip")
+PROBE_LIB = os.path.join(HERE, "libaoresp_probe.so")
+
+
+def build_probe(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    cmd = ["hipcc", *FLAGS, "-shared", "-x", "hip", PROBE_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{err}")
+    os.replace(tmp, PROBE_LIB)
+    if verbose:
+        print("built", PROBE_LIB)
+    return PROBE_LIB
+
+
 # Device check programs that the GPU tests run (test code, not part of the library).
 CHECKS = {"recip_check": os.path.join(os.path.dirname(HERE), "tests", "recip_check.hip")}
 
@@ -75,4 +94,5 @@ def build_checks(verbose: bool = False) -> list:
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_probe(verbose=True)
     build_checks(verbose=True)

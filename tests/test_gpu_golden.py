@@ -5,7 +5,9 @@ The benchmark's launch (n = 10^6, 90% outliers, G = 1024, 64 x 64
 refinement, 3600 angle bins) is compared whole: every row of the coarse
 accumulator by digest, its vote total, the refinement grid row by row, the
 angle histogram, and the result bit for bit, under the default work split and
-under the split the autotuner picks (as the benchmark does).
+under the split the autotuner picks (as the benchmark does).  The
+multi-rotation workload (three rotations, 70% outliers, top-3, radius 5) is
+compared on its coarse grid and its three results.
 """
 import hashlib
 import json
@@ -89,3 +91,21 @@ def test_paper_scale_solve_whole(aor, tuned):
     assert st == 0
     assert_result(r, g, m.cpu().numpy())
     aor.tuner_clear()
+
+
+def test_multi_rotation_paper_scale(aor):
+    gold = load("c3_seed3000.json")
+    wl = gold["params"]
+    inst = make_input(wl)
+    P = torch.from_numpy(inst.P).cuda()
+    Q = torch.from_numpy(inst.Q).cuda()
+    grid = aor.coarse_grid(P, Q, wl["G"])
+    torch.cuda.synchronize()
+    assert_grid_rows(grid.cpu().numpy(), gold["coarse_rows"], gold["coarse_sum"])
+    prm = aor.SolveParams(grid=wl["G"], refine_grid=wl["M"], refine_halfwin=wl["w"], angle_bins=wl["B"],
+                          nms_radius=wl["rad"], inlier_thresh=wl["tau"])
+    outs, masks, st = aor.est_rotations_topk(P, Q, wl["k"], prm)
+    masks = masks.cpu().numpy()
+    assert [[o["peak_cell"], o["axis_votes"]] for o in outs] == gold["peaks"]
+    for t, (o, g) in enumerate(zip(outs, gold["results"])):
+        assert_result(o, g, masks[t])

@@ -391,6 +391,31 @@ def test_batch_graph_replayed_on_new_data(aor):
             assert_result_equal(outs3[t], outs[t])
 
 
+def test_determinism_repeat_and_permutation(aor):
+    """Repeated solves give identical bits, and a permutation of the
+    correspondences gives the identical accumulator, result and (permuted)
+    mask: every count is an integer sum and every float a fixed expression,
+    whatever the work split and the order in which work-groups run."""
+    inst = synth.make_instance(200000, 4321, outlier_rate=0.9)
+    prm = aor.SolveParams(grid=1024, refine_grid=64, angle_bins=3600)
+    P, Q = dev(inst.P), dev(inst.Q)
+    base = aor.solve_debug(P, Q, prm)
+    for _ in range(3):
+        again = aor.solve_debug(P, Q, prm)
+        assert torch.equal(again["grid"], base["grid"]) and torch.equal(again["fine"], base["fine"])
+        assert torch.equal(again["hist"], base["hist"]) and torch.equal(again["mask"], base["mask"])
+        assert_result_equal(again["result"], base["result"])
+        assert np.array_equal(np.asarray(again["result"]["R_ls"]).view(np.uint32),
+                              np.asarray(base["result"]["R_ls"]).view(np.uint32))
+    perm = np.random.default_rng(5).permutation(inst.n)
+    Pp, Qp = dev(inst.P[:, perm]), dev(inst.Q[:, perm])
+    other = aor.solve_debug(Pp, Qp, prm)
+    assert torch.equal(other["grid"], base["grid"]) and torch.equal(other["fine"], base["fine"])
+    assert torch.equal(other["hist"], base["hist"])
+    assert_result_equal(other["result"], base["result"])
+    assert np.array_equal(other["mask"].cpu().numpy(), base["mask"].cpu().numpy()[perm])
+
+
 # ------------------------------------------------------ full size, sampled
 def test_paper_scale_sampled_parity(aor, orc):
     """n = 1e6, G = 1024 + 64x64 refinement, B = 3600 (the benchmark's launch
