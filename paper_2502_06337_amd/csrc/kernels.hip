@@ -105,15 +105,12 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 // quarter owns).
 struct CoarseEmit {
     static constexpr bool kAudit = false;
+    static constexpr bool kPairedLines = true;
     uint32_t* tile;
     int jofs, sw;          // sw = G + 1 words per line pair, jofs = -(band0 / 2) * sw
     int clo, chi;          // allowed cross indices (callers skip a walk when chi < clo)
     uint32_t* sink;        // this lane's word of a scratch row that is never flushed
     int qa = 0, qb = 0;    // clean-state cell offsets relative to clo
-    struct Cursor {
-        uint32_t* p;       // word row of the line, shifted by clo
-        uint32_t inc;      // 1 on an even line, 1 << 16 on an odd one
-    };
     __device__ __forceinline__ uint32_t* row_of(int j) const { return tile + ((int)__umul24(j >> 1, sw) + jofs); }
     __device__ __forceinline__ static uint32_t inc_of(int j) { return 1u << ((j & 1) << 4); }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
@@ -124,23 +121,24 @@ struct CoarseEmit {
 #pragma unroll 1
         for (int k = klo; k <= khi; ++k) atomicAdd(row + k, inc);
     }
-    __device__ __forceinline__ Cursor start(int j, int off) {
+    // word row of line j's pair, shifted by clo
+    __device__ __forceinline__ uint32_t* row_start(int j, int off) {
         qa = off - 1 - clo;
         qb = -off - clo;
-        return Cursor{row_of(j) + clo, inc_of(j)};
+        return row_of(j) + clo;
     }
-    // the next line: the other half of the same word row after an even line,
-    // the low half of the next word row after an odd one
-    __device__ __forceinline__ Cursor next(Cursor c) const {
-        return Cursor{c.p + __umul24(c.inc >> 16, sw), c.inc ^ 0x10001u};
-    }
-    // cells r - 1 + off and, if second, r - off; a cell outside the allowed
-    // range goes to the lane's sink word instead (no divergent branch)
-    __device__ __forceinline__ void pair(Cursor c, int r, bool second) const {
+    __device__ __forceinline__ uint32_t* next_row(uint32_t* row) const { return row + sw; }
+    // cells r - 1 + off and, if second, r - off of the line with parity H
+    // (low half of the word for H = 0, high half for H = 1); a cell outside
+    // the allowed range goes to the lane's sink word instead (no divergent
+    // branch)
+    template <int H>
+    __device__ __forceinline__ void pair_h(uint32_t* row, int r, bool second) const {
+        constexpr uint32_t inc = 1u << (16 * H);
         const unsigned span = (unsigned)(chi - clo);
         const int a = r + qa, b = r + qb;
-        atomicAdd((unsigned)a <= span ? c.p + a : sink, c.inc);
-        atomicAdd(second && (unsigned)b <= span ? c.p + b : sink, c.inc);
+        atomicAdd((unsigned)a <= span ? row + a : sink, inc);
+        atomicAdd(second && (unsigned)b <= span ? row + b : sink, inc);
     }
 };
 
@@ -574,6 +572,7 @@ __global__ void k_peak_finish(const Inst* __restrict__ insts, int ninst, const u
 
 struct FineEmit {
     static constexpr bool kAudit = false;
+    static constexpr bool kPairedLines = false;
     uint32_t* tile;
     int mode, M;
     float U0, V0, hx, hy;

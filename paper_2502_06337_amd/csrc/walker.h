@@ -383,7 +383,10 @@ AOR_HD __forceinline__ void walk_search(float aL, float bL, float c, int sel, fl
 // Emitter interface: start(j, off) returns a cursor for line j (and may set
 // up the pair offsets for this octant), next(cursor) advances it by a line,
 // pair(cursor, r, second) emits the clean-state cells, and emit(j, klo, khi)
-// a general range.  An emitter with kAudit set also receives, on every clean
+// a general range.  An emitter with kPairedLines set stores lines 2m and
+// 2m + 1 in one row m instead: row_start(j, off) returns the row of line j,
+// next_row(row) the following one, and pair_h<H>(row, r, second) emits the
+// clean-state cells of the line with parity H in that row.  An emitter with kAudit set also receives, on every clean
 // line, the values at the two rows next to the evaluated one (audit(fb, fa)),
 // so that a host test can check what the certificates claim.  kLattice: every vertex coordinate y0 + k*hy is exact and
 // so are sums of them (the coarse grid), so the evaluated row's coordinate is
@@ -429,9 +432,10 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
     // of these two values instead of a select of 1 - off / -off times hy
     __asm__("" : "+v"(dy_up), "+v"(dy_dn));
 #endif
-    auto cur = emit.start(cs, off);
     float lastf = clean0 ? kCleanMark : 0.0f;
-    for (int j = cs; j < ce; ++j, cur = emit.next(cur)) {
+    // One cell line j.  clean_pair(r, second) emits the clean-state cells of
+    // the line; general ranges go to emit(j, klo, khi).
+    auto step = [&](int j, auto&& clean_pair) {
         x += hx;
         xx = x * x;
         ax = sa * x;
@@ -445,11 +449,11 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
                            vertex_F(sb, sc, xx, ax, y0 + (float)(r + 1) * hy));
             }
             const bool up = f > 0.0f;
-            emit.pair(cur, r, up != (off != 0));
+            clean_pair(r, up != (off != 0));
             r += (up ? 1 : 0) - off;
             if (kLattice) yr += up ? dy_up : dy_dn;
             lastf = f;
-            continue;
+            return;
         }
         const bool clean = fabsf(lastf) > T;
         cb = (cert & 1) != 0;
@@ -486,7 +490,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
                 lastf = (cb1 && ca1) ? kCleanMark : 0.0f;
                 r = lo - off;
                 if (kLattice) yr = y0 + (float)r * hy;
-                continue;
+                return;
             }
         }
         // General step.  Rows that may change side on line j+1 (all others
@@ -532,6 +536,28 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         lastf = (cb1 && ca1 && hi == lo - 1) ? kCleanMark : 0.0f;
         r = lo - off;
         if (kLattice) yr = y0 + (float)r * hy;
+    };
+    if constexpr (Emit::kPairedLines) {
+        // Lines 2m and 2m + 1 share the emitter's row m: walk them in pairs,
+        // so that the row advances once per pair and each half of the pair
+        // has a fixed slot (an odd first line and an even last line alone).
+        auto row = emit.row_start(cs, off);
+        int j = cs;
+        if (j & 1) {
+            step(j, [&](int rr, bool s2) { emit.template pair_h<1>(row, rr, s2); });
+            ++j;
+            row = emit.next_row(row);
+        }
+        for (; j + 1 < ce; j += 2) {
+            step(j, [&](int rr, bool s2) { emit.template pair_h<0>(row, rr, s2); });
+            step(j + 1, [&](int rr, bool s2) { emit.template pair_h<1>(row, rr, s2); });
+            row = emit.next_row(row);
+        }
+        if (j < ce) step(j, [&](int rr, bool s2) { emit.template pair_h<0>(row, rr, s2); });
+    } else {
+        auto cur = emit.start(cs, off);
+        for (int j = cs; j < ce; ++j, cur = emit.next(cur))
+            step(j, [&](int rr, bool s2) { emit.pair(cur, rr, s2); });
     }
 }
 

@@ -46,6 +46,7 @@ std::vector<int16_t> disk_ranges(int G) {
 
 struct CoarseHostEmit {
     static constexpr bool kAudit = true;
+    static constexpr bool kPairedLines = true;   // the line-pair loop of the coarse kernel
     uint32_t* grid;
     const int16_t* disk;
     int mode, G, clo, chi;
@@ -67,6 +68,14 @@ struct CoarseHostEmit {
         (*this)(j, r - 1 + offs, r - 1 + offs);
         if (second) (*this)(j, r - offs, r - offs);
     }
+    // rows are line pairs: the row handle is the even line
+    int row_start(int j, int off) {
+        offs = off;
+        return j & ~1;
+    }
+    int next_row(int row) const { return row + 2; }
+    template <int H>
+    void pair_h(int row, int r, bool second) { pair(row + H, r, second); }
     void audit(float below, float above) {
         counts->steps++;
         if (!(below > 0.0f)) counts->violations++;
@@ -76,6 +85,7 @@ struct CoarseHostEmit {
 
 struct FineHostEmit {
     static constexpr bool kAudit = true;
+    static constexpr bool kPairedLines = false;
     uint32_t* tile;
     int mode, M;
     float U0, V0, hx, hy;
