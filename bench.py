@@ -245,9 +245,9 @@ def bench_topk(aor, synth, torch, reps: int) -> dict:
 def bench_batch(aor, synth, torch, reps: int) -> dict:
     """256 instances, n log-uniform in [1e3, 1e5], outlier rate in [0.5, 0.95],
     sigma in [0.001, 0.02]; G per instance = aoresp_grid_for_n(n) (the swept
-    table).  Batched calls (one captured graph over all instances; the first
-    call plans and records it, later calls with the same layout launch it as
-    it is) against a loop of one-at-a-time device solves over the same
+    table).  Batched calls (one graph over all instances: the first call of a
+    layout plans and runs it eagerly, the second records it, later ones launch
+    the recording) against a loop of one-at-a-time device solves over the same
     inputs, both on resident data."""
     insts = synth.batch_instances(256, synth.config_seed(4, 0))
     sizes = [i.n for i in insts]
@@ -264,12 +264,12 @@ def bench_batch(aor, synth, torch, reps: int) -> dict:
     torch.cuda.synchronize()
     tb, tf, tl = [], [], []
     for _ in range(reps):
-        # first call after other work: plans and records the graph
+        # first call after other work: plans and runs eagerly
         t0 = time.perf_counter()
         aor.est_rotation_batch(P, Q, off, prm, want_mask=False)
         torch.cuda.synchronize()
         tf.append(time.perf_counter() - t0)
-        # the same layout again: the recorded graph is launched as it is
+        # the same layout again: recorded once, then launched as recorded
         for _ in range(3):
             t0 = time.perf_counter()
             aor.est_rotation_batch(P, Q, off, prm, want_mask=False)

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -646,6 +647,61 @@ aoresp_status launch_plan_graph(DeviceCtx* ctx, Workspace& w, const Plan& plan, 
     return AORESP_OK;
 }
 
+std::vector<uint64_t> plan_key(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps,
+                               const int* npk, const float* P, const float* Q, const uint8_t* masks) {
+    std::vector<uint64_t> key;
+    key.reserve(4 + 7 * (size_t)ninst);
+    key.push_back((uint64_t)ninst);
+    key.push_back((uint64_t)(uintptr_t)P);
+    key.push_back((uint64_t)(uintptr_t)Q);
+    key.push_back((uint64_t)(uintptr_t)masks);
+    for (int b = 0; b < ninst; ++b) {
+        const ResolvedParams& r = rps[b];
+        uint32_t tau_bits;
+        std::memcpy(&tau_bits, &r.tau, 4);
+        const Tuning tu = tuning_for(ctx, r.G, off[b + 1] - off[b]);
+        uint64_t vt;
+        std::memcpy(&vt, &tu.vote_target, 8);
+        key.push_back((uint64_t)off[b + 1] | (uint64_t)npk[b] << 40);
+        key.push_back((uint64_t)r.G | (uint64_t)r.M << 16 | (uint64_t)r.w << 32 | (uint64_t)r.rad << 40);
+        key.push_back((uint64_t)r.B | (uint64_t)r.F << 16 | (uint64_t)r.gate << 40 | (uint64_t)r.rule << 48);
+        key.push_back((uint64_t)r.J | (uint64_t)tau_bits << 32);
+        key.push_back((uint64_t)tu.tile_cells);
+        key.push_back(vt);
+    }
+    return key;
+}
+
+aoresp_status run_plan(DeviceCtx* ctx, Workspace& w, std::vector<uint64_t>&& key, const int64_t* off, int ninst,
+                       const ResolvedParams* rps, const int* npk, const float* P, const float* Q, uint8_t* masks,
+                       hipStream_t s, Plan& scratch, const Plan** used) {
+    aoresp_status st;
+    if (w.gexec && w.gen == w.replay_gen && key == w.replay_key) {
+        AOR_HIP(hipGraphLaunch(w.gexec, s));
+        *used = &w.replay_plan;
+        return AORESP_OK;
+    }
+    const bool again = w.gen == w.last_gen && key == w.last_key;
+    if ((st = build_plan(ctx, off, ninst, rps, npk, scratch)) != AORESP_OK) return st;
+    if (again) {
+        // the same layout twice in a row: record it for the calls to come
+        w.replay_key.clear();
+        if ((st = launch_plan_graph(ctx, w, scratch, P, Q, masks, s)) != AORESP_OK) return st;
+        w.replay_key = std::move(key);
+        w.replay_gen = w.gen;
+        w.replay_plan = std::move(scratch);
+        w.last_key.clear();
+        *used = &w.replay_plan;
+        return AORESP_OK;
+    }
+    if ((st = enqueue_plan(ctx, w, scratch, P, Q, masks, s)) != AORESP_OK) return st;
+    if ((st = fetch_plan(w, scratch, s)) != AORESP_OK) return st;
+    w.last_key = std::move(key);
+    w.last_gen = w.gen;
+    *used = &scratch;
+    return AORESP_OK;
+}
+
 void plan_buffers(Workspace& w, const Plan& plan, BufNeed* out) {
     const size_t nn = plan.N > 0 ? (size_t)plan.N : 1;
     const OutLayout ol(plan.nres);
@@ -736,10 +792,21 @@ aoresp_status solve_dev_common(const float* P, const float* Q, size_t n, uint32_
     Plan plan;
     int64_t off[2] = {0, (int64_t)n};
     int npk = (int)k;
-    if ((st = build_plan(ctx, off, 1, &rp, &npk, plan)) != AORESP_OK) return st;
-    if ((st = enqueue_plan(ctx, ctx->ws, plan, P, Q, masks, s, marks, grid_out, fine_out, hist_out)) != AORESP_OK) return st;
     std::vector<int> valid;
-    if ((st = finish_plan(ctx->ws, plan, out, valid, s)) != AORESP_OK) return st;
+    if (marks || grid_out || fine_out || hist_out) {
+        // stage marks or debug copies: an eager run
+        if ((st = build_plan(ctx, off, 1, &rp, &npk, plan)) != AORESP_OK) return st;
+        if ((st = enqueue_plan(ctx, ctx->ws, plan, P, Q, masks, s, marks, grid_out, fine_out, hist_out)) != AORESP_OK)
+            return st;
+        if ((st = finish_plan(ctx->ws, plan, out, valid, s)) != AORESP_OK) return st;
+    } else {
+        const Plan* used = nullptr;
+        if ((st = run_plan(ctx, ctx->ws, plan_key(ctx, off, 1, &rp, &npk, P, Q, masks), off, 1, &rp, &npk, P, Q, masks,
+                           s, plan, &used)) != AORESP_OK)
+            return st;
+        AOR_HIP(hipStreamSynchronize(s));
+        if ((st = collect_plan(ctx->ws, *used, out, valid)) != AORESP_OK) return st;
+    }
     uint32_t found = 0;
     while (found < k && valid[found]) ++found;
     if (k_found) *k_found = found;

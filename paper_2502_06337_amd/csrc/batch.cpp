@@ -6,10 +6,10 @@
 // updated in place for the next batch).  Instance b's result is bit-identical
 // to est_rotation on its own columns with the same parameters: the kernels
 // are the same and each instance only touches its own grid, windows and
-// histograms.  A call with the same layout as the previous batched call on
-// the device (offsets, parameters, work splits, device pointers), with no
-// other solve in between, launches the recorded graph again without planning
-// or capturing.
+// histograms.  A layout (offsets, parameters, work splits, device pointers)
+// that comes twice in a row on the device, with no other solve in between,
+// is recorded as one graph and launched again while it keeps coming, without
+// planning or capturing.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -61,47 +61,14 @@ static aoresp_status batch_common(const float* P, const float* Q, const uint64_t
         dQ = w.Q.as<float>();
         dM = masks ? w.masks.as<uint8_t>() : nullptr;
     }
-    // What the recorded graph depends on: offsets, resolved parameters, the
-    // coarse vote's work split per instance and the device pointers.
-    std::vector<uint64_t> key;
-    key.reserve(4 + 12 * (size_t)batch);
-    key.push_back(batch);
-    key.push_back((uint64_t)(uintptr_t)dP);
-    key.push_back((uint64_t)(uintptr_t)dQ);
-    key.push_back((uint64_t)(uintptr_t)dM);
-    for (uint32_t b = 0; b < batch; ++b) {
-        const ResolvedParams& r = rps[b];
-        uint32_t tau_bits;
-        std::memcpy(&tau_bits, &r.tau, 4);
-        const Tuning tu = tuning_for(ctx, r.G, offs[b + 1] - offs[b]);
-        uint64_t vt;
-        std::memcpy(&vt, &tu.vote_target, 8);
-        key.push_back((uint64_t)offs[b + 1]);
-        key.push_back((uint64_t)r.G | (uint64_t)r.M << 16 | (uint64_t)r.w << 32 | (uint64_t)r.rad << 40);
-        key.push_back((uint64_t)r.B | (uint64_t)r.F << 16 | (uint64_t)r.gate << 40 | (uint64_t)r.rule << 48);
-        key.push_back((uint64_t)r.J | (uint64_t)tau_bits << 32);
-        key.push_back((uint64_t)tu.tile_cells);
-        key.push_back(vt);
-    }
-    const Plan* plan_used;
-    if (w.gexec && w.gen == w.replay_gen && key == w.replay_key) {
-        // the same batch layout as the last recorded call, and nothing else
-        // has used the workspace since: launch the recorded graph again
-        if (hipGraphLaunch(w.gexec, s) != hipSuccess) return AORESP_EDEVICE;
-        plan_used = &w.replay_plan;
-    } else {
-        Plan plan;
-        if ((st = build_plan(ctx, offs.data(), (int)batch, rps.data(), npk.data(), plan)) != AORESP_OK) return st;
-        // the whole batched pipeline as one captured graph
-        if ((st = launch_plan_graph(ctx, w, plan, dP, dQ, dM, s)) != AORESP_OK) {
-            w.replay_key.clear();
-            return st;
-        }
-        w.replay_key = std::move(key);
-        w.replay_gen = w.gen;
-        w.replay_plan = std::move(plan);
-        plan_used = &w.replay_plan;
-    }
+    // the whole batched pipeline, recorded as one graph once the same layout
+    // comes twice in a row and launched again while it keeps coming
+    Plan scratch;
+    const Plan* plan_used = nullptr;
+    if ((st = run_plan(ctx, w, plan_key(ctx, offs.data(), (int)batch, rps.data(), npk.data(), dP, dQ, dM),
+                       offs.data(), (int)batch, rps.data(), npk.data(), dP, dQ, dM, s, scratch, &plan_used)) !=
+        AORESP_OK)
+        return st;
     const Plan& plan = *plan_used;
     if (host && masks && N && hipMemcpyAsync(masks, w.masks.ptr, N, hipMemcpyDeviceToHost, s) != hipSuccess)
         return AORESP_EDEVICE;

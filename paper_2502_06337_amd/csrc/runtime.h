@@ -134,6 +134,8 @@ struct Workspace {
     std::vector<uint64_t> replay_key;
     uint64_t replay_gen = 0;
     Plan replay_plan;
+    std::vector<uint64_t> last_key;     // key of the last call run eagerly (recorded if it comes again)
+    uint64_t last_gen = 0;
 };
 
 
@@ -207,6 +209,20 @@ struct BufNeed {
 };
 void plan_buffers(Workspace& w, const Plan& plan, BufNeed* out);
 size_t plan_blob_bytes(const Plan& plan);
+// What a recorded plan depends on: offsets, peaks per instance, resolved
+// parameters, the coarse vote's work split per instance and the device
+// pointers of the inputs and masks.
+std::vector<uint64_t> plan_key(DeviceCtx* ctx, const int64_t* off, int ninst, const ResolvedParams* rps,
+                               const int* npk, const float* P, const float* Q, const uint8_t* masks);
+// Run a plan's pipeline and result copy on s (caller holds ctx->mu):
+// a call whose key equals the one recorded last in w, with no other use of w
+// in between, launches the recorded graph again without planning; one whose
+// key equals the previous eager call's is planned, recorded and launched;
+// any other is planned and enqueued directly.  *used points to the plan the
+// results are read with (valid until the next call on w).
+aoresp_status run_plan(DeviceCtx* ctx, Workspace& w, std::vector<uint64_t>&& key, const int64_t* off, int ninst,
+                       const ResolvedParams* rps, const int* npk, const float* P, const float* Q, uint8_t* masks,
+                       hipStream_t s, Plan& scratch, const Plan** used);
 // enqueue_plan + fetch_plan captured into one hipGraph and launched on s
 // (caller holds ctx->mu; no stage marks or debug copies).
 aoresp_status launch_plan_graph(DeviceCtx* ctx, Workspace& w, const Plan& plan, const float* P, const float* Q,
