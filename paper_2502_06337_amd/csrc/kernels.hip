@@ -904,10 +904,9 @@ __device__ __forceinline__ bool sample_cell(const float* a1, const float* a2, fl
     if (!(s2 <= 0.0f)) return false;
     const float rinv = recip_1_4(1.0f - s2);
     const float u = s0 * rinv, v = s1 * rinv;
-    ix = (int)floorf((u + 1.0f) * hg);
-    iy = (int)floorf((v + 1.0f) * hg);
-    ix = ix < 0 ? 0 : (ix > G - 1 ? G - 1 : ix);
-    iy = iy < 0 ? 0 : (iy > G - 1 ? G - 1 : iy);
+    // |u|, |v| <= 1 here, so the rounded-down conversion is floor exactly
+    ix = max(0, min(__float2int_rd((u + 1.0f) * hg), G - 1));
+    iy = max(0, min(__float2int_rd((v + 1.0f) * hg), G - 1));
     return true;
 }
 
@@ -991,40 +990,33 @@ __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ 
     }
 }
 
-// Band pass: one work item = (instance, band of rows [r0, r1), circles
-// [c0, c1)).  A wave takes one circle at a time (its record loaded while the
-// previous circle is walked), finds the checkpoint intervals whose rows may
-// reach the band, and walks only their samples, 64 per step, with the exact
-// per-sample cell, counting them in the LDS tile.  The tile is then stored
-// whole to the item's slot of the partial arena (no global atomics).
-__global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ insts, const int4* __restrict__ items,
-                                                      const uint32_t* __restrict__ recs,
-                                                      uint32_t* __restrict__ part) {
-    extern __shared__ __align__(16) uint32_t sm[];
-    const int4 wi = items[blockIdx.x];
-    const Inst& I = insts[wi.x];
-    const int G = I.G, J = I.J, bw = I.sbw;
-    const int band = wi.y;
-    const int r0 = band * bw, r1 = r0 + bw;
-    const int cells = bw * G;
-    const bool half = I.shalf != 0;   // 16-bit counters: cells 2m and 2m + 1 share word m
-    const int words = half ? cells >> 1 : cells;
-    // LDS: the sample directions (when they fit), then the band tile
-    const bool lds_dirs = I.sdir_lds != 0;
-    float* ldir = reinterpret_cast<float*>(sm);
-    uint32_t* tile = sm + (lds_dirs ? 2 * J : 0);
-    for (int e = threadIdx.x; e < words; e += blockDim.x) tile[e] = 0u;
-    if (lds_dirs)
-        for (int e = threadIdx.x; e < J; e += blockDim.x) {
-            ldir[e] = I.scs[e];
-            ldir[J + e] = I.ssn[e];
-        }
-    __syncthreads();
-    const float* cs = lds_dirs ? ldir : I.scs;
-    const float* sn = lds_dirs ? ldir + J : I.ssn;
+// The circles of a band item, walked by the waves of its work-group into the
+// band tile.  kLdsDirs: the sample directions were staged in LDS (else they
+// are read from global memory); kHalf: 16-bit counters, cells 2m and 2m + 1
+// in word m.  Each wave walks 64 samples per step with the exact per-sample
+// cell; the directions of the next step are loaded into the other of two
+// register pairs while this step is evaluated.
+typedef const float __attribute__((address_space(1))) global_float;
+
+template <bool kLdsDirs, bool kHalf>
+__device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, const uint32_t* __restrict__ recs,
+                                                 const float* ldir, uint32_t* tile, int r0, int r1) {
+    const int G = I.G, J = I.J;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
+    const global_float* gcs = (const global_float*)I.scs;
+    const global_float* gsn = (const global_float*)I.ssn;
+    auto dir = [&](int j, float& c, float& sn) {
+        const int idx = j >= J ? j - J : j;
+        if (kLdsDirs) {
+            c = ldir[idx];
+            sn = ldir[J + idx];
+        } else {
+            c = gcs[idx];
+            sn = gsn[idx];
+        }
+    };
     // the next circle's record is loaded while the current one is walked
     int64_t li = wi.z + wave;
     uint32_t hn = 0u;
@@ -1055,46 +1047,75 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
         const int ck = (lane * L) / 63, cn = ((lane + 1) * L) / 63;
         const bool hit = lane < 63 && cn > ck && hi >= r0 && lo < r1;
         unsigned long long mask = __ballot(hit);
+        // one sample: its cell in the band tile, or nothing
+        auto vote = [&](int j, float c, float sn) {
+            if (j >= 0) {
+                int ix, iy;
+                if (sample_cell(a1, a2, c, sn, G, hg, ix, iy) && iy >= r0 && iy < r1) {
+                    // LDS atomics: lanes of a run of equal cells serialise on
+                    // one address, which costs less here than merging the run
+                    const int cell = (int)__umul24((uint32_t)(iy - r0), (uint32_t)G) + ix;
+                    if (kHalf) atomicAdd(&tile[cell >> 1], 1u << ((cell & 1) << 4));
+                    else atomicAdd(&tile[cell], 1u);
+                }
+            }
+        };
         while (mask) {
             const int k = __builtin_ctzll(mask);
             const int e = k + __builtin_ctzll(~(mask >> k));   // bit 63 is never set
             mask &= ~(((1ull << (e - k)) - 1ull) << k);
             const int jb = js + (k * L) / 63, je = js + (e * L) / 63;
-            // the directions of the next step are loaded while this one is evaluated
-            float cnx = 0.0f, snx = 0.0f;
-            {
-                const int j = jb + lane;
-                const int idx = j >= J ? j - J : j;
-                if (j < je) {
-                    cnx = cs[idx];
-                    snx = sn[idx];
-                }
-            }
-            for (int j0 = jb; j0 < je; j0 += 64) {
-                const int j = j0 + lane;
-                const float c_cur = cnx, s_cur = snx;
-                {
-                    const int jn = j + 64;
-                    const int idn = jn >= J ? jn - J : jn;
-                    if (jn < je) {
-                        cnx = cs[idn];
-                        snx = sn[idn];
-                    }
-                }
-                int cell = -1;
-                if (j < je) {
-                    int ix, iy;
-                    if (sample_cell(a1, a2, c_cur, s_cur, G, hg, ix, iy) && iy >= r0 && iy < r1)
-                        cell = (iy - r0) * G + ix;
-                }
-                // LDS atomics: lanes of a run of equal cells serialise on one
-                // address, which costs less here than merging the run first
-                if (cell >= 0) {
-                    if (half) atomicAdd(&tile[cell >> 1], 1u << ((cell & 1) << 4));
-                    else atomicAdd(&tile[cell], 1u);
-                }
+            // two register pairs of directions: step t uses one while step
+            // t + 1 is loaded into the other
+            float ca = 0.0f, sa = 0.0f, cb = 0.0f, sb = 0.0f;
+            if (jb + lane < je) dir(jb + lane, ca, sa);
+            for (int j0 = jb; j0 < je; j0 += 128) {
+                const int ja = j0 + lane, jn = ja + 64, jm = ja + 128;
+                if (jn < je) dir(jn, cb, sb);
+                vote(ja < je ? ja : -1, ca, sa);
+                if (j0 + 64 >= je) break;   // uniform
+                if (jm < je) dir(jm, ca, sa);
+                vote(jn < je ? jn : -1, cb, sb);
             }
         }
+    }
+}
+
+// Band pass: one work item = (instance, band of rows [r0, r1), circles
+// [c0, c1)).  A wave takes one circle at a time (its record loaded while the
+// previous circle is walked), finds the checkpoint intervals whose rows may
+// reach the band, and walks only their samples, 64 per step, with the exact
+// per-sample cell, counting them in the LDS tile.  The tile is then stored
+// whole to the item's slot of the partial arena (no global atomics).
+__global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ insts, const int4* __restrict__ items,
+                                                      const uint32_t* __restrict__ recs,
+                                                      uint32_t* __restrict__ part) {
+    extern __shared__ __align__(16) uint32_t sm[];
+    const int4 wi = items[blockIdx.x];
+    const Inst& I = insts[wi.x];
+    const int G = I.G, J = I.J, bw = I.sbw;
+    const int band = wi.y;
+    const int r0 = band * bw, r1 = r0 + bw;
+    const int cells = bw * G;
+    const bool half = I.shalf != 0;   // 16-bit counters: cells 2m and 2m + 1 share word m
+    const int words = half ? cells >> 1 : cells;
+    // LDS: the sample directions (when they fit), then the band tile
+    const bool lds_dirs = I.sdir_lds != 0;
+    float* ldir = reinterpret_cast<float*>(sm);
+    uint32_t* tile = sm + (lds_dirs ? 2 * J : 0);
+    for (int e = threadIdx.x; e < words; e += blockDim.x) tile[e] = 0u;
+    if (lds_dirs)
+        for (int e = threadIdx.x; e < J; e += blockDim.x) {
+            ldir[e] = I.scs[e];
+            ldir[J + e] = I.ssn[e];
+        }
+    __syncthreads();
+    if (lds_dirs) {
+        if (half) sample_band_walk<true, true>(I, wi, recs, ldir, tile, r0, r1);
+        else sample_band_walk<true, false>(I, wi, recs, ldir, tile, r0, r1);
+    } else {
+        if (half) sample_band_walk<false, true>(I, wi, recs, ldir, tile, r0, r1);
+        else sample_band_walk<false, false>(I, wi, recs, ldir, tile, r0, r1);
     }
     __syncthreads();
     const int chunk = wi.z / I.schunk;
