@@ -308,6 +308,7 @@ aoresp_status build_plan_with(DeviceCtx* ctx, const int64_t* off, int ninst, con
         I.st = at->st;
         if (I.npk > plan.max_npk) plan.max_npk = I.npk;
         if (rp.M > plan.maxM) plan.maxM = rp.M;
+        if (rp.G > plan.maxG) plan.maxG = rp.G;
         size_t lds = (size_t)rp.B * 8 + (size_t)I.npk * rp.B * 4;
         if (lds > 160 * 1024) return AORESP_EINVAL;
         if (lds > hist_lds) hist_lds = lds;
@@ -526,7 +527,7 @@ aoresp_status enqueue_plan(DeviceCtx* ctx, Workspace& w, const Plan& plan, const
     mark(2);
     if (plan.max_npk > 1)
         launch_local_max(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), w.lmax.as<uint32_t>(),
-                         s);
+                         plan.maxG, s);
     for (int t = 0; t < plan.max_npk; ++t) {
         launch_peak(w.grid.as<uint32_t>(), insts, cell_items, (int)plan.cell_items.size(), stt, t,
                     w.lmax.as<uint32_t>(), keys, s);

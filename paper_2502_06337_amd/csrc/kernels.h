@@ -137,7 +137,7 @@ void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, VoteQueues 
 // read the local-maximum bitmap of instances with npk > 1, written once by
 // launch_local_max over the same items.
 void launch_local_max(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, uint32_t* lmax,
-                      hipStream_t s);
+                      int maxG, hipStream_t s);
 void launch_peak(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, const PeakState* st,
                  int slot, const uint32_t* lmax, unsigned long long* keys, hipStream_t s);
 void launch_peak_finish(const Inst* insts, int ninst, const unsigned long long* keys, PeakState* st, int slot,

@@ -467,26 +467,89 @@ __device__ __forceinline__ unsigned long long block_max_u64(unsigned long long k
     return b;
 }
 
-// Local-maximum bitmap of cells [c0, c1) of an instance with several peaks:
-// bit c set iff cell c holds a vote and is a local maximum within radius rad.
-// A wave covers 64 consecutive cells (item bounds are multiples of 64), so its
-// ballot is two words of the bitmap.
+// Local-maximum bitmap of an instance with several peaks: bit c set iff
+// cell c holds a vote and is a local maximum within radius rad.  A work-group
+// takes the whole rows [c0/G, c1/G) of a cell item (item bounds are whole
+// rows) and the 64 columns blockIdx.y * 64 + [0, 64): it stages those cells
+// with a margin of rad cells (zero outside the grid, which never beats a cell
+// with a vote) in LDS and tests every disk neighbour of each cell without
+// early exits, so that neighbouring lanes advance together.  A wave's 64
+// lanes cover 64 consecutive cells of a row, so its ballot is two words of
+// the bitmap.  Radii above kLocalMaxLdsRad read the grid directly.
+constexpr int kLocalMaxLdsRad = 32;
+constexpr int kLocalMaxRows = 64;   // rows of a cell item at most (8192 cells, G >= 128; or the 64 x 64 grid)
+
+size_t local_max_lds_bytes() {
+    return ((size_t)(kLocalMaxRows + 2 * kLocalMaxLdsRad) * (64 + 2 * kLocalMaxLdsRad) + 2 * kLocalMaxLdsRad + 1) * 4;
+}
+
 __global__ __launch_bounds__(256) void k_local_max(const uint32_t* __restrict__ grid_arena,
                                                    const Inst* __restrict__ insts, const int4* __restrict__ items,
                                                    uint32_t* __restrict__ lmax) {
+    extern __shared__ __align__(16) uint32_t lm[];
     const int4 wi = items[blockIdx.x];
     const Inst& I = insts[wi.x];
     if (I.npk < 2) return;
+    const int G = I.G, rad = I.rad;
+    const int x0 = (int)blockIdx.y * 64;
+    if (x0 >= G) return;
     const uint32_t* a = grid_arena + I.grid_off;
-    const int G = I.G;
-    const int lane = threadIdx.x & 63;
-    for (int c0 = wi.y + (int)(threadIdx.x & ~63u); c0 < wi.z; c0 += blockDim.x) {
-        const int c = c0 + lane;
-        const uint32_t v = a[c];
-        const bool f = v != 0u && local_max(a, G, I.rad, c % G, c / G, v);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int y0 = wi.y / G, nr = (wi.z - wi.y) / G;
+    if (rad > kLocalMaxLdsRad) {
+        for (int r = wave; r < nr; r += nwaves) {
+            const int c = (y0 + r) * G + x0 + lane;
+            const uint32_t v = a[c];
+            const bool f = v != 0u && local_max(a, G, rad, x0 + lane, y0 + r, v);
+            const unsigned long long m = __ballot(f);
+            if (lane == 0) {
+                uint32_t* out = lmax + I.lmax_off + ((c - lane) >> 5);
+                out[0] = (uint32_t)m;
+                out[1] = (uint32_t)(m >> 32);
+            }
+        }
+        return;
+    }
+    int* ext = reinterpret_cast<int*>(lm);   // half-width of the disk on row dy, at ext[dy + rad]
+    uint32_t* tile = lm + 2 * kLocalMaxLdsRad + 1;
+    const int TW = 64 + 2 * rad, TH = nr + 2 * rad;
+    for (int d = threadIdx.x; d <= 2 * rad; d += blockDim.x) {
+        const int dy = d - rad, rem = rad * rad - dy * dy;
+        int dx = 0;
+        while ((dx + 1) * (dx + 1) <= rem) ++dx;
+        ext[d] = dx;
+    }
+    for (int t = threadIdx.x; t < TW * TH; t += blockDim.x) {
+        const int ty = t / TW, tx = t - ty * TW;
+        const int gy = y0 - rad + ty, gx = x0 - rad + tx;
+        tile[t] = (gy >= 0 && gy < G && gx >= 0 && gx < G) ? a[gy * G + gx] : 0u;
+    }
+    __syncthreads();
+    for (int r = wave; r < nr; r += nwaves) {
+        const uint32_t* centre = tile + (r + rad) * TW + rad + lane;
+        const uint32_t v = *centre;
+        bool f = v != 0u;
+        // rows above: any neighbour with as many votes comes first (lower index)
+        for (int dy = -rad; dy < 0; ++dy) {
+            const int e = ext[dy + rad];
+            const uint32_t* row = centre + dy * TW;
+            for (int dx = -e; dx <= e; ++dx) f &= row[dx] < v;
+        }
+        // the cell's own row: equal counts on the left come first
+        {
+            const int e = ext[rad];
+            for (int dx = -e; dx < 0; ++dx) f &= centre[dx] < v;
+            for (int dx = 1; dx <= e; ++dx) f &= centre[dx] <= v;
+        }
+        // rows below: equal counts come later
+        for (int dy = 1; dy <= rad; ++dy) {
+            const int e = ext[dy + rad];
+            const uint32_t* row = centre + dy * TW;
+            for (int dx = -e; dx <= e; ++dx) f &= row[dx] <= v;
+        }
         const unsigned long long m = __ballot(f);
         if (lane == 0) {
-            uint32_t* out = lmax + I.lmax_off + (c0 >> 5);
+            uint32_t* out = lmax + I.lmax_off + (((y0 + r) * G + x0) >> 5);
             out[0] = (uint32_t)m;
             out[1] = (uint32_t)(m >> 32);
         }
@@ -1691,6 +1754,7 @@ void init_kernel_attributes() {
     // the kernels that take more than the default dynamic LDS; done once per
     // device before any launch (and so outside any stream capture)
     set_lds_limit((const void*)k_vote);
+    set_lds_limit((const void*)k_local_max);
     set_lds_limit((const void*)k_fine_vote);
     set_lds_limit((const void*)k_angle_hist);
     set_lds_limit((const void*)k_angle_fine_hist);
@@ -1730,9 +1794,10 @@ void launch_vote(ArcRecs recs, const Inst* insts, const int4* items, VoteQueues 
 }
 
 void launch_local_max(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, uint32_t* lmax,
-                      hipStream_t s) {
+                      int maxG, hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(k_local_max, dim3((unsigned)nitems), dim3(256), 0, s, grid_arena, insts, items, lmax);
+    hipLaunchKernelGGL(k_local_max, dim3((unsigned)nitems, (unsigned)((maxG + 63) / 64)), dim3(256),
+                       local_max_lds_bytes(), s, grid_arena, insts, items, lmax);
 }
 
 void launch_peak(const uint32_t* grid_arena, const Inst* insts, const int4* items, int nitems, const PeakState* st,

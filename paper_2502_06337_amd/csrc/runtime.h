@@ -100,7 +100,7 @@ struct Plan {
     size_t grid_cells = 0, fine_cells = 0, hist_cells = 0;
     size_t fhist_cells = 0;    // fine-angle windows, after the histograms in the same arena
     int nres = 0;              // result slots (sum of npk)
-    int max_npk = 0, maxM = 0;
+    int max_npk = 0, maxM = 0, maxG = 0;
     size_t hist_lds = 0;
     size_t fhist_lds = 0;      // 0: no instance refines its angle
     size_t sample_lds = 0;     // LDS of the sampling band pass (0: no instance uses the sampling rule)

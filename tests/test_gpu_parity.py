@@ -279,12 +279,13 @@ def test_topk_local_maxima_rim_axis(aor, orc):
         assert np.array_equal(masks[t], b["mask"])
 
 
-@pytest.mark.parametrize("rad", [1, 3, 12])
+@pytest.mark.parametrize("rad", [1, 3, 12, 32, 40])
 def test_topk_radius_parity(aor, orc, rad):
-    """Local maxima within radii of 1, 3 and 12 cells (disk rows clipped at the
-    grid edge, ties between equal counts at small n), up to 6 peaks."""
+    """Local maxima within radii of 1 to 40 cells (disk rows clipped at the
+    grid edge, ties between equal counts at small n; radii above 32 take the
+    kernel's path without LDS staging), up to 6 peaks."""
     inst = synth.make_instance(2500, 400 + rad, n_rot=3, inlier_frac_each=0.1, sigma=0.02)
-    G, B, k = 64 if rad == 12 else 128, 360, 6
+    G, B, k = 64 if rad in (12, 32) else 128, 360, 6
     prm = aor.SolveParams(grid=G, angle_bins=B, nms_radius=rad)
     outs, masks, st = aor.est_rotations_topk(dev(inst.P), dev(inst.Q), k, prm)
     masks = masks.cpu().numpy()
