@@ -24,7 +24,12 @@ constexpr int kMaxPeaks = 8;
 // counter takes at most one vote per correspondence of its work item, so items
 // are capped at kMaxItemArcs (< 2^16) correspondences and never overflow it.
 constexpr int kTileCells = 65536;         // 16-bit cells of one band tile (128 KiB)
-constexpr int kTileWords = kTileCells / 2 + 128;   // + padding: bw/2 pairs of G + 1 words, bw <= 256
+// Words between two rows of a tile (and before the first, after the last)
+// that take the cells a certified walk counts just outside the frame.
+constexpr int kTilePad = 7;
+// kTilePad + bw/2 rows of G + kTilePad words (bw G <= kTileCells, bw <= 256),
+// rounded up to 16 bytes
+constexpr int kTileWords = (kTileCells / 2 + 129 * kTilePad + 3) & ~3;
 constexpr int kMaxItemArcs = 63 * 1024;
 constexpr int kVoteThreads = 1024;
 constexpr int kCountSlots = 64;   // partial inlier counters per result

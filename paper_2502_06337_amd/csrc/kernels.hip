@@ -97,20 +97,26 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 
 // Cells of a band tile: 16-bit counters, the cells (j, k) and (j + 1, k) of
 // an even/odd line pair in the low and high half of one word, word rows of
-// Sw = G + 1 words per line pair (pair m, cross k at m * Sw + k).  The lanes
-// of a wave (different curves, mostly on the same line) hit spread-out banks,
-// and the column pass's flush, which reads across lines, is conflict-free too.
-// Cells outside the disk are counted here and dropped at the flush, so the
-// walk only clips to the frame (and, in the row pass, to the columns its
-// quarter owns).
+// Sw = G + kTilePad words per line pair (pair m, cross k at word kTilePad +
+// m * Sw + k).  Sw is odd, so the lanes of a wave (different curves, mostly on
+// the same line) hit spread-out banks and the column pass's flush, which reads
+// across lines, is conflict-free.  The kTilePad words between rows take the
+// cells that a clean line counts outside the frame, so the clean path writes
+// without a bound check: a certified body's octant is clipped to the frame
+// plus two cells and a line, and its crossing moves by at most one cell per
+// line, so its cells have cross indices -4 .. G + 4; in the row pass its
+// lines also stop short of the columns owned by the column quarters
+// (kCoarseRowShrink).  Pads are never flushed, and cells outside the disk are
+// counted here and dropped at the flush.
 struct CoarseEmit {
     static constexpr bool kAudit = false;
     static constexpr bool kPairedLines = true;
-    uint32_t* tile;
-    int jofs, sw;          // sw = G + 1 words per line pair, jofs = -(band0 / 2) * sw
-    int clo, chi;          // allowed cross indices (callers skip a walk when chi < clo)
-    uint32_t* sink;        // this lane's word of a scratch row that is never flushed
-    int qa = 0, qb = 0;    // clean-state cell offsets relative to clo
+    uint32_t* tile;        // cross index 0 of the band's first line pair
+    int jofs, sw;          // sw = G + kTilePad words per line pair, jofs = -(band0 / 2) * sw
+    int clo, chi;          // allowed cross indices of a general range (callers skip a walk when chi < clo)
+    int db = 0;            // second cell of a clean line relative to its first: 1 - 2 off
+    int sh = 0;            // cell k of a row handle at handle[k + sh]: 1 - off
+    uint32_t d_up = 0, d_dn = 0, e_up = 0, e_dn = 0;   // pair2's increments by each line's step
     __device__ __forceinline__ uint32_t* row_of(int j) const { return tile + ((int)__umul24(j >> 1, sw) + jofs); }
     __device__ __forceinline__ static uint32_t inc_of(int j) { return 1u << ((j & 1) << 4); }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
@@ -121,24 +127,42 @@ struct CoarseEmit {
 #pragma unroll 1
         for (int k = klo; k <= khi; ++k) atomicAdd(row + k, inc);
     }
-    // word row of line j's pair, shifted by clo
+    // word row of line j's pair, shifted so that row[r] is cell r - 1 + off
     __device__ __forceinline__ uint32_t* row_start(int j, int off) {
-        qa = off - 1 - clo;
-        qb = -off - clo;
-        return row_of(j) + clo;
+        db = 1 - 2 * off;
+        sh = 1 - off;
+        d_up = off ? 0x10000u : 0x10001u;
+        d_dn = off ? 0x10001u : 0x10000u;
+        e_up = off ? 0u : 0x10000u;
+        e_dn = off ? 0x10000u : 0u;
+        return row_of(j) + (off - 1);
     }
     __device__ __forceinline__ uint32_t* next_row(uint32_t* row) const { return row + sw; }
+    __device__ __forceinline__ uint32_t* rows_after(uint32_t* row, int n) const { return row + n * sw; }
+    // a general range of the line with parity H
+    template <int H>
+    __device__ __forceinline__ void range_h(uint32_t* row, int klo, int khi) const {
+        constexpr uint32_t inc = 1u << (16 * H);
+        uint32_t* base = row + sh;
+        klo = max(klo, clo);
+        khi = min(khi, chi);
+#pragma unroll 1
+        for (int k = klo; k <= khi; ++k) atomicAdd(base + k, inc);
+    }
     // cells r - 1 + off and, if second, r - off of the line with parity H
-    // (low half of the word for H = 0, high half for H = 1); a cell outside
-    // the allowed range goes to the lane's sink word instead (no divergent
-    // branch)
+    // (low half of the word for H = 0, high half for H = 1)
     template <int H>
     __device__ __forceinline__ void pair_h(uint32_t* row, int r, bool second) const {
         constexpr uint32_t inc = 1u << (16 * H);
-        const unsigned span = (unsigned)(chi - clo);
-        const int a = r + qa, b = r + qb;
-        atomicAdd((unsigned)a <= span ? row + a : sink, inc);
-        atomicAdd(second && (unsigned)b <= span ? row + b : sink, inc);
+        atomicAdd(row + r, inc);
+        atomicAdd(row + r + db, second ? inc : 0u);
+    }
+    // both lines of the row from rows r0 -> r1 -> r2: the line 2m + 1 cell
+    // r1 - 1 + off shares its word with line 2m's second cell, if any
+    __device__ __forceinline__ void pair2(uint32_t* row, int r0, int r1, int r2, bool up0, bool up1) const {
+        atomicAdd(row + r0, 1u);
+        atomicAdd(row + r1, up0 ? d_up : d_dn);
+        atomicAdd(row + r2, up1 ? e_up : e_dn);
     }
 };
 
@@ -160,11 +184,10 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
     __shared__ int group_next;   // next unclaimed group of 64 correspondences
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    uint32_t* tile = smem;
+    uint32_t* tile = smem + kTilePad;
     uint32_t* rbody = smem + kTileWords + wid * (kRingBody + kRingLine);
     uint32_t* rline = rbody + kRingBody;
-    uint32_t* sinkrow = smem + kTileWords + kWaves * (kRingBody + kRingLine);   // 64 words, never read
-    int16_t* dlim = reinterpret_cast<int16_t*>(sinkrow + 64);
+    int16_t* dlim = reinterpret_cast<int16_t*>(smem + kTileWords + kWaves * (kRingBody + kRingLine));
     uint32_t bad = 0;
 
     // the queue of this work-group's XCD first; its chunks' records stay in
@@ -196,11 +219,11 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
         const int bw = I.bw;
         const int band0 = band * bw;
         const int bwb = (band0 + bw <= G) ? bw : (G - band0);
-        const int Sw = G + 1;                // words per line pair
-        const int tile_words = (bwb >> 1) * Sw;
+        const int Sw = G + kTilePad;         // words per line pair
+        const int tile_words = kTilePad + (bwb >> 1) * Sw;
         const int lbw = 31 - __clz(bwb), lg = 31 - __clz(G);   // both powers of two
         const float h = 2.0f / (float)G;
-        for (int t = tid; t < tile_words; t += kVoteThreads) tile[t] = 0u;
+        for (int t = tid; t < tile_words; t += kVoteThreads) smem[t] = 0u;
         for (int t = tid; t < bwb; t += kVoteThreads) {
             dlim[2 * t] = I.disk[2 * (band0 + t)];
             dlim[2 * t + 1] = I.disk[2 * (band0 + t) + 1];
@@ -241,10 +264,10 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     int s, e;
                     unpack_range(pr, s, e);
                     int dir, slo, shi;
-                    octant_walk_info(mode, p, geo2, dir, slo, shi);
+                    octant_walk_info(mode, p, geo2, dir, slo, shi, kCoarseRowShrink);
                     const int2 pp = piece_part(max(s, band0), min(e, band0 + bwb), slo, shi, part);
                     const int sel = p >> 1;
-                    CoarseEmit em{tile, -(band0 >> 1) * Sw, Sw, 0, G - 1, sinkrow + lane};
+                    CoarseEmit em{tile, -(band0 >> 1) * Sw, Sw, 0, G - 1};
                     float aL = abc.x, bL = abc.y;
                     if (mode == 1) {
                         int ja, jb;
@@ -323,8 +346,8 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                     // the body range depends on the octant only through its parity
                     const int4 geo = R.geo[base + li];
                     int d;
-                    octant_walk_info(mode, 0, geo, d, slo_e, shi_e);
-                    octant_walk_info(mode, 1, geo, d, slo_o, shi_o);
+                    octant_walk_info(mode, 0, geo, d, slo_e, shi_e, kCoarseRowShrink);
+                    octant_walk_info(mode, 1, geo, d, slo_o, shi_o, kCoarseRowShrink);
                 }
                 step = __ballot(any) ? 0 : 4;
                 if (!any) li = nli;   // nothing of this one in the band
@@ -1742,7 +1765,7 @@ __global__ void k_zero_list(ZeroList zl) {
 size_t coarse_lds_bytes() {
     // tile (bw / 2 line pairs of G + 1 words, bw <= 256) + per-wave rings
     // (u32) + sink row + in-disk limits (2 x int16 per band line, <= 256 lines)
-    return (size_t)kTileWords * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 64 * 4 + 2 * 2 * 256;
+    return (size_t)kTileWords * 4 + (size_t)(kVoteThreads / 64) * (kRingBody + kRingLine) * 4 + 2 * 2 * 256;
 }
 
 static void set_lds_limit(const void* fn) {

@@ -64,16 +64,23 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
 
 // Certification threshold of the coarse walk, T = 1.2e-6 (|a| + |b| + |c|); a
 // refinement grid uses 1.5 T.  Evaluated vertices have |u| <= 1 and |v| <=
-// 1 + 4h <= 1.125 (the crossing stays within the frame plus the clip margin),
-// so |W| <= 1.27.  Let E bound the binary32 error of F at a vertex with
-// sigma*F > T.  On the coarse lattice W is exact; the products c*W, a*u, b*v,
-// the inner sum and the outer sum each round once (relative 2^-24), and the
-// doubling is exact, so |F~ - F| <= 2^-24 (1.27 |c| + 4.5 (|a| + |b|)) +
-// 2^-24 |F~|, and near the threshold E <= 4.5 * 2^-24 (|a| + |b| + |c|).  A
-// refinement grid rounds W as well (at most 2^-22, times |c|), so there
-// E <= 5.3 * 2^-24 (|a| + |b| + |c|).
+// 1 + 5h <= 1.16 (the crossing stays within the frame plus the clip margin
+// and the walk evaluates the row next to it), so |W| <= 1.35.  Let E bound
+// the binary32 error of F at a vertex with sigma*F > T, and S = |a| + |b| +
+// |c|.  On the coarse lattice W is exact; the products c*W, a*u, b*v, the
+// inner sum and the outer sum each round once (relative 2^-24), and the
+// doubling is exact, so |F~ - F| <= 2^-24 (1.35 |c| + 4.7 (|a| + |b|)) +
+// 2^-24 |F~|, and near the threshold E <= 4.7 * 2^-24 S.  A refinement grid
+// rounds W as well (at most 2^-22, times |c|), so there E <= 5.4 * 2^-24 S.
+// The coarse walk's line pairs use the Horner form of vertex_F_fast instead:
+// fma(c, x, 2a) and fma(c, y, 2b) round once each (at most 2^-24 (|c| +
+// 2|a|) and 2^-24 (1.16 |c| + 2|b|)), K = fma(., x, -c) once more (2^-24
+// (2|c| + 2|a|)) and the result once, so its error is at most 2^-24 (4.35 |c|
+// + 4 |a| + 2.32 |b|) + 2^-24 |F~| <= 4.4 * 2^-24 S near the threshold.  A
+// fast value beyond T (= 20.1 * 2^-24 S) is at least 15.7 * 2^-24 S from zero
+// in exact arithmetic, more than E, so vertex_F has its sign.
 // (i) sigma*F > T gives an exact F > T - E; along a vertex line |dF/dy| =
-// 2 |c y + b| <= L = 2 (1.125 |c| + |b|) <= 3.01 |d|, so the vertex lies
+// 2 |c y + b| <= L = 2 (1.16 |c| + |b|) <= 3.07 |d|, so the vertex lies
 // beyond the curve by a cross gap g >= (T - E) / L.  (ii) The gap carries over
 // to the row of the next line that the certificate speaks for, and on an
 // octant of slope <= 1 a cross gap g means a distance >= g / sqrt(2) from the
@@ -81,12 +88,21 @@ AOR_HD __forceinline__ uint32_t classify(float a, float b, float c) {
 // R = |d| / c >= 1) |F| = c |rho - R| (rho + R) >= 2 |d| delta (1 - delta / 2R),
 // and |F| = 2 |d| delta for a line, so binary32 gets the sign of every vertex
 // farther than E / (1.99 |d|).  T must therefore exceed
-// E (1 + sqrt(2) L / (1.99 |d|)) <= 3.14 E: 8.4e-7 (|a| + |b| + |c|) on the
-// coarse lattice and 9.9e-7 on a refinement grid, margins of 1.42x and 1.8x.
+// E (1 + sqrt(2) L / (1.99 |d|)) <= 3.19 E: 8.9e-7 S on the coarse lattice
+// (for either evaluation) and 1.03e-6 S on a refinement grid, margins of 1.34x
+// and 1.75x.
 AOR_HD __forceinline__ float cert_threshold(float a, float b, float c) {
     return 1.2e-6f * ((fabsf(a) + fabsf(b)) + fabsf(c));
 }
 constexpr float kFineCertScale = 1.5f;   // refinement grids certify with 1.5 T
+
+// sigma*F at vertex (x, y) in Horner form, from sc = sigma c, tsa = 2 sigma a,
+// tsb = 2 sigma b and nsc = -sigma c: fma(fma(sc, y, tsb), y, fma(fma(sc, x,
+// tsa), x, nsc)).  Not the rule's binary32 value, but within 4.4 * 2^-24 S of
+// the exact one near the threshold, so a value beyond T has vertex_F's sign.
+AOR_HD __forceinline__ float vertex_F_fast(float sc, float tsa, float tsb, float nsc, float x, float y) {
+    return fmaf(fmaf(sc, y, tsb), y, fmaf(fmaf(sc, x, tsa), x, nsc));
+}
 
 // Octant pieces of the curve of (a, b, c) (c >= 0; not degenerate, not risky)
 // in the frame u = u0 + j*hu (j in [0, nu]), v = v0 + k*hv (k in [0, nv]).
@@ -194,7 +210,18 @@ AOR_HD inline void circle_pieces(float af, float bf, float cf, uint32_t flags, d
 
 // Direction of the transition index along octant p (+1 grows, -1 shrinks) and
 // the vertex lines [lo, hi] on which the octant is monotone with |slope| <= 1.
-AOR_HD __forceinline__ void octant_walk_info(int mode, int p, const int4& geo, int& dir, int& slo, int& shi) {
+// A row octant's range loses `shrink` lines at its end away from the extreme
+// point (next to the 45-degree point, where its cells meet the columns owned
+// by the column pieces).  With shrink = 2 on the coarse lattice no cell of the
+// remaining lines reaches an owned column: on vertex row k of the lower
+// u-root with |v_k - cv| <= qv - 2h the crossing lies left of cu - qu by
+// sqrt(r^2 - (qv - 2h)^2) - qu >= 4h (qv - h) / ((1 + 1/sqrt(2)) r) >= 1.58 h
+// (qu = qv = r / sqrt(2), r >= 1, h <= 1/32), so its cell index is at most
+// ceil((cu - qu - u0) / h) - 2 = ja - 2; the upper u-root mirrors this with
+// cells >= jb + 1.  The walk therefore needs no column bound on those lines.
+constexpr int kCoarseRowShrink = 2;
+AOR_HD __forceinline__ void octant_walk_info(int mode, int p, const int4& geo, int& dir, int& slo, int& shi,
+                                             int shrink = 0) {
     int ja, jb, jm, km, ka, kb;
     unpack_range(geo.x, ja, jb);
     unpack_range(geo.y, jm, km);
@@ -212,8 +239,8 @@ AOR_HD __forceinline__ void octant_walk_info(int mode, int p, const int4& geo, i
         slo = (p & 1) ? jm + 1 : ja;
         shi = (p & 1) ? jb : jm;
     } else {
-        slo = (p & 1) ? km + 1 : ka;
-        shi = (p & 1) ? kb : km;
+        slo = (p & 1) ? km + 1 : ka + shrink;
+        shi = (p & 1) ? kb - shrink : km;
     }
 }
 
@@ -385,8 +412,12 @@ AOR_HD __forceinline__ void walk_search(float aL, float bL, float c, int sel, fl
 // pair(cursor, r, second) emits the clean-state cells, and emit(j, klo, khi)
 // a general range.  An emitter with kPairedLines set stores lines 2m and
 // 2m + 1 in one row m instead: row_start(j, off) returns the row of line j,
-// next_row(row) the following one, and pair_h<H>(row, r, second) emits the
-// clean-state cells of the line with parity H in that row.  An emitter with kAudit set also receives, on every clean
+// next_row(row) the following one, rows_after(row, n) the n-th following
+// one, range_h<H>(row, klo, khi) emits a general range of the line with
+// parity H in that row, pair_h<H>(row, r, second) its clean-state cells, and
+// pair2(row, r0, r1, r2, up0, up1) those of both lines of a row walked
+// clean from row r0 (line 2m: cell r0 - 1 + off, and r1 - 1 + off if it
+// differs; line 2m + 1: cell r1 - 1 + off, and r2 - 1 + off if it differs).  An emitter with kAudit set also receives, on every clean
 // line, the values at the two rows next to the evaluated one (audit(fb, fa)),
 // so that a host test can check what the certificates claim.  kLattice: every vertex coordinate y0 + k*hy is exact and
 // so are sums of them (the coarse grid), so the evaluated row's coordinate is
@@ -433,15 +464,16 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
     __asm__("" : "+v"(dy_up), "+v"(dy_dn));
 #endif
     float lastf = clean0 ? kCleanMark : 0.0f;
-    // One cell line j.  clean_pair(r, second) emits the clean-state cells of
-    // the line; general ranges go to emit(j, klo, khi).
-    auto step = [&](int j, auto&& clean_pair) {
+    // One cell line.  clean = fabsf(lastf) > T (the caller's, so that a
+    // comparison it already made is not repeated); clean_pair(r, second)
+    // emits the clean-state cells of the line, range(klo, khi) a general range.
+    auto step = [&](bool clean, auto&& range, auto&& clean_pair) {
         x += hx;
         xx = x * x;
         ax = sa * x;
         // evaluated on every lane; only clean lanes use it
         const float f = vertex_F(sb, sc, xx, ax, kLattice ? yr : y0 + (float)r * hy);
-        if (fabsf(lastf) > T && f != 0.0f) {
+        if (clean && f != 0.0f) {
             if constexpr (Emit::kAudit) {
                 // test builds only: the certificates vouch for sigma*F > 0 at
                 // row r - 1 and sigma*F < 0 at row r + 1 of this line
@@ -455,7 +487,6 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             lastf = f;
             return;
         }
-        const bool clean = fabsf(lastf) > T;
         cb = (cert & 1) != 0;
         ca = (cert & 2) != 0;
         if (!clean && lastf != 0.0f) {
@@ -483,7 +514,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             const bool cb1 = lo1 == r0 ? true : ((lo1 == r0 + 1 ? f0 : f1) > T);
             const bool ca1 = lo1 == r0 + 2 ? true : ((lo1 == r0 ? f0 : f1) < -T);
             if (f0 != 0.0f && f1 != 0.0f && !(f0 < 0.0f && f1 > 0.0f) && (cb1 || ca1)) {
-                emit(j, (lo < lo1 ? lo : lo1) - 1, (lo > lo1 ? lo : lo1) - 1);
+                range((lo < lo1 ? lo : lo1) - 1, (lo > lo1 ? lo : lo1) - 1);
                 lo = lo1;
                 hi = lo1 - 1;
                 cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
@@ -529,7 +560,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
                 if (!cb1 || !ca1) bad |= 4u;
             }
         }
-        emit(j, (lo < lo1 ? lo : lo1) - 1, hi > hi1 ? hi : hi1);
+        range((lo < lo1 ? lo : lo1) - 1, hi > hi1 ? hi : hi1);
         lo = lo1;
         hi = hi1;
         cert = (cb1 ? 1 : 0) | (ca1 ? 2 : 0);
@@ -541,23 +572,65 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         // Lines 2m and 2m + 1 share the emitter's row m: walk them in pairs,
         // so that the row advances once per pair and each half of the pair
         // has a fixed slot (an odd first line and an even last line alone).
+        // A pair whose state is clean and whose two fast values (vertex_F_fast,
+        // the second at the row the first one moves to) both lie beyond T is
+        // decided by their signs and emitted at once; any other pair goes line
+        // by line through the exact step.
+        static_assert(kLattice, "line pairs are walked on the coarse lattice");
+        const float tsa = 2.0f * sa, tsb = 2.0f * sb, nsc = -sc;
         auto row = emit.row_start(cs, off);
+        auto range0 = [&](int klo, int khi) { emit.template range_h<0>(row, klo, khi); };
+        auto range1 = [&](int klo, int khi) { emit.template range_h<1>(row, klo, khi); };
+        auto pair0 = [&](int rr, bool s2) { emit.template pair_h<0>(row, rr, s2); };
+        auto pair1 = [&](int rr, bool s2) { emit.template pair_h<1>(row, rr, s2); };
         int j = cs;
         if (j & 1) {
-            step(j, [&](int rr, bool s2) { emit.template pair_h<1>(row, rr, s2); });
+            step(fabsf(lastf) > T, range1, pair1);
             ++j;
             row = emit.next_row(row);
         }
-        for (; j + 1 < ce; j += 2) {
-            step(j, [&](int rr, bool s2) { emit.template pair_h<0>(row, rr, s2); });
-            step(j + 1, [&](int rr, bool s2) { emit.template pair_h<1>(row, rr, s2); });
-            row = emit.next_row(row);
+        const auto row_end = emit.rows_after(row, (ce - j) >> 1);
+        const bool last_alone = ((ce - j) & 1) != 0;
+        for (; row != row_end; row = emit.next_row(row)) {
+            const float xa = x + hx, xb = xa + hx;
+            const float f0 = vertex_F_fast(sc, tsa, tsb, nsc, xa, yr);
+            const bool up0 = f0 > 0.0f;
+            const float y1 = yr + (up0 ? dy_up : dy_dn);
+            const float f1 = vertex_F_fast(sc, tsa, tsb, nsc, xb, y1);
+            const bool clean = fabsf(lastf) > T;
+            if (clean && fabsf(f0) > T && fabsf(f1) > T) {
+                const bool up1 = f1 > 0.0f;
+                const int r1 = r + (up0 ? 1 : 0) - off;
+                const int r2 = r1 + (up1 ? 1 : 0) - off;
+                if constexpr (Emit::kAudit) {
+                    // test builds only: the rule's values agree in sign with the
+                    // fast ones, and the certificates hold on both lines
+                    const float xxa = xa * xa, axa = sa * xa, xxb = xb * xb, axb = sa * xb;
+                    const float ea = vertex_F(sb, sc, xxa, axa, yr), eb = vertex_F(sb, sc, xxb, axb, y1);
+                    emit.audit(up0 ? ea : -ea, -1.0f);
+                    emit.audit(up1 ? eb : -eb, -1.0f);
+                    emit.audit(vertex_F(sb, sc, xxa, axa, y0 + (float)(r - 1) * hy),
+                               vertex_F(sb, sc, xxa, axa, y0 + (float)(r + 1) * hy));
+                    emit.audit(vertex_F(sb, sc, xxb, axb, y0 + (float)(r1 - 1) * hy),
+                               vertex_F(sb, sc, xxb, axb, y0 + (float)(r1 + 1) * hy));
+                }
+                emit.pair2(row, r, r1, r2, up0, up1);
+                r = r2;
+                yr = y1 + (up1 ? dy_up : dy_dn);
+                x = xb;
+                // the state stays clean: lastf keeps a value beyond T
+            } else {
+                step(clean, range0, pair0);
+                step(fabsf(lastf) > T, range1, pair1);
+            }
         }
-        if (j < ce) step(j, [&](int rr, bool s2) { emit.template pair_h<0>(row, rr, s2); });
+        if (last_alone) step(fabsf(lastf) > T, range0, pair0);
     } else {
         auto cur = emit.start(cs, off);
-        for (int j = cs; j < ce; ++j, cur = emit.next(cur))
-            step(j, [&](int rr, bool s2) { emit.pair(cur, rr, s2); });
+        int j = cs;
+        auto range = [&](int klo, int khi) { emit(j, klo, khi); };
+        auto pair = [&](int rr, bool s2) { emit.pair(cur, rr, s2); };
+        for (; j < ce; ++j, cur = emit.next(cur)) step(fabsf(lastf) > T, range, pair);
     }
 }
 

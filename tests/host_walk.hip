@@ -59,14 +59,16 @@ struct CoarseHostEmit {
         khi = khi > chi ? chi : khi;
         for (int k = klo; k <= khi; ++k) grid[mode == 0 ? (size_t)k * G + j : (size_t)j * G + k] += 1;
     }
-    int start(int j, int off) {
-        offs = off;
-        return j;
-    }
-    int next(int j) const { return j + 1; }
-    void pair(int j, int r, bool second) {
-        (*this)(j, r - 1 + offs, r - 1 + offs);
-        if (second) (*this)(j, r - offs, r - offs);
+    // A cell of a clean line: the kernel writes it without a bound check, into
+    // its tile's pad words when it lies outside the grid.  A cell beyond the
+    // column bound of a row quarter, or farther out than the pads reach, is
+    // counted as the kernel would count it and recorded as a violation.
+    void clean_cell(int j, int k) {
+        const bool lo_ok = clo > 0 ? k >= clo : k >= -kTilePad;
+        const bool hi_ok = chi < G - 1 ? k <= chi : k <= G - 1 + kTilePad;
+        if (!lo_ok || !hi_ok) counts->violations++;
+        if (k < 0 || k >= G || k < disk[2 * j] || k > disk[2 * j + 1]) return;
+        grid[mode == 0 ? (size_t)k * G + j : (size_t)j * G + k] += 1;
     }
     // rows are line pairs: the row handle is the even line
     int row_start(int j, int off) {
@@ -74,8 +76,20 @@ struct CoarseHostEmit {
         return j & ~1;
     }
     int next_row(int row) const { return row + 2; }
+    int rows_after(int row, int n) const { return row + 2 * n; }
     template <int H>
-    void pair_h(int row, int r, bool second) { pair(row + H, r, second); }
+    void range_h(int row, int klo, int khi) { (*this)(row + H, klo, khi); }
+    template <int H>
+    void pair_h(int row, int r, bool second) {
+        clean_cell(row + H, r - 1 + offs);
+        if (second) clean_cell(row + H, r - offs);
+    }
+    void pair2(int row, int r0, int r1, int r2, bool up0, bool up1) {
+        clean_cell(row, r0 - 1 + offs);
+        if (up0 != (offs != 0)) clean_cell(row, r1 - 1 + offs);
+        clean_cell(row + 1, r1 - 1 + offs);
+        if (up1 != (offs != 0)) clean_cell(row + 1, r2 - 1 + offs);
+    }
     void audit(float below, float above) {
         counts->steps++;
         if (!(below > 0.0f)) counts->violations++;
@@ -189,7 +203,7 @@ int hw_coarse_grid(const float* P, const float* Q, long n, int G, uint32_t* grid
                 }
                 const float aL = mode == 0 ? a : b, bL = mode == 0 ? b : a;
                 int dir, slo, shi;
-                octant_walk_info(mode, p, geo, dir, slo, shi);
+                octant_walk_info(mode, p, geo, dir, slo, shi, kCoarseRowShrink);
                 for (int b0 = 0; b0 < G; b0 += bw) {
                     const int cs = s > b0 ? s : b0, ce = e < b0 + bw ? e : b0 + bw;
                     if (cs >= ce) continue;

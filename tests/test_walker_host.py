@@ -128,6 +128,20 @@ def test_certificate_audit_at_scale(hw, G):
     assert audit[1] == 0
 
 
+@pytest.mark.parametrize("G", [128, 4096])
+def test_clean_cells_within_bounds(hw, G):
+    """Uniformly oriented great circles and adversarial ones: no clean line of
+    a certified walk counts a cell past its row quarter's column bound or
+    beyond the tile's pad words (the kernel writes those cells unchecked), and
+    every fast value beyond the threshold has the rule's sign."""
+    rng = np.random.default_rng(31 + G)
+    D = np.concatenate([rng.normal(size=(3, 3000)), adversarial(rng, 1000)], axis=1).astype(np.float32)
+    Z = np.zeros_like(D)
+    g, bad, audit = host_coarse(hw, D, Z, G)
+    assert bad == 0
+    assert audit[0] > 1e6 and audit[1] == 0
+
+
 def test_ls_rotation_solve_matches_oracle(hw, orc):
     """The library's quaternion solve (host build) against the oracle's SVD
     solve on the same float64 sums: equal to a few float32 rounding steps."""
