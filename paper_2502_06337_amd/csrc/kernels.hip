@@ -979,9 +979,25 @@ __device__ __forceinline__ bool sample_frame(const float* p, const float* q, flo
     return true;
 }
 
+// floor(x) as an int in one instruction (x finite, |x| < 2^31)
+__device__ __forceinline__ int floor_to_int(float x) {
+    int r;
+    __asm__("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// x clamped to [0, hi] (hi >= 0 and the same on every lane) in one instruction
+__device__ __forceinline__ int clamp_int(int x, int hi) {
+    int r;
+    __asm__("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(x), "s"(hi));
+    return r;
+}
+
 // Cell of sample s = alpha1 cos + alpha2 sin, or false on the open northern
 // hemisphere: projection from the north pole (Eq. (7)) as
 // (s_x, s_y) * (1 / (1 - s_z)), cell floor((u + 1) G/2) clamped to [0, G-1].
+// (u + 1) G/2 is one fused multiply-add u hg + hg: hg = G/2 is a power of
+// two, so rounding u hg + hg once gives round(u + 1) hg, the rule's value.
 __device__ __forceinline__ bool sample_cell(const float* a1, const float* a2, float c, float sn, int G, float hg,
                                             int& ix, int& iy) {
     const float s0 = (a1[0] * c) + (a2[0] * sn);
@@ -990,9 +1006,9 @@ __device__ __forceinline__ bool sample_cell(const float* a1, const float* a2, fl
     if (!(s2 <= 0.0f)) return false;
     const float rinv = recip_1_4(1.0f - s2);
     const float u = s0 * rinv, v = s1 * rinv;
-    // |u|, |v| <= 1 here, so the rounded-down conversion is floor exactly
-    ix = max(0, min(__float2int_rd((u + 1.0f) * hg), G - 1));
-    iy = max(0, min(__float2int_rd((v + 1.0f) * hg), G - 1));
+    // |u|, |v| <= 1 here (up to rounding), so both values are small and finite
+    ix = clamp_int(floor_to_int(__builtin_fmaf(u, hg, hg)), G - 1);
+    iy = clamp_int(floor_to_int(__builtin_fmaf(v, hg, hg)), G - 1);
     return true;
 }
 
@@ -1082,8 +1098,6 @@ __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ 
 // in word m.  Each wave walks 64 samples per step with the exact per-sample
 // cell; the directions of the next step are loaded into the other of two
 // register pairs while this step is evaluated.
-typedef const float __attribute__((address_space(1))) global_float;
-
 template <bool kLdsDirs, bool kHalf>
 __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, const uint32_t* __restrict__ recs,
                                                  const float* ldir, uint32_t* tile, int r0, int r1) {
@@ -1091,16 +1105,18 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
-    const global_float* gcs = (const global_float*)I.scs;
-    const global_float* gsn = (const global_float*)I.ssn;
+    // buffer resources over the direction tables (J floats each): one 32-bit
+    // offset per sample addresses both, and reads past the end return 0
+    const __amdgpu_buffer_rsrc_t rcs = __builtin_amdgcn_make_buffer_rsrc((void*)I.scs, (short)0, 4 * J, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsn = __builtin_amdgcn_make_buffer_rsrc((void*)I.ssn, (short)0, 4 * J, 0x00020000);
+    // direction j (0 <= j < J: a run that passes J is split there)
     auto dir = [&](int j, float& c, float& sn) {
-        const int idx = j >= J ? j - J : j;
         if (kLdsDirs) {
-            c = ldir[idx];
-            sn = ldir[J + idx];
+            c = ldir[j];
+            sn = ldir[J + j];
         } else {
-            c = gcs[idx];
-            sn = gsn[idx];
+            c = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rcs, j << 2, 0, 0));
+            sn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsn, j << 2, 0, 0));
         }
     };
     // the next circle's record is loaded while the current one is walked
@@ -1134,35 +1150,42 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
         const bool hit = lane < 63 && cn > ck && hi >= r0 && lo < r1;
         unsigned long long mask = __ballot(hit);
         // one sample: its cell in the band tile, or nothing
-        auto vote = [&](int j, float c, float sn) {
-            if (j >= 0) {
-                int ix, iy;
-                if (sample_cell(a1, a2, c, sn, G, hg, ix, iy) && iy >= r0 && iy < r1) {
+        const unsigned rows = (unsigned)(r1 - r0);
+        auto vote = [&](bool valid, float c, float sn) {
+            int ix, iy;
+            if (valid && sample_cell(a1, a2, c, sn, G, hg, ix, iy)) {
+                const int ry = iy - r0;
+                if ((unsigned)ry < rows) {
                     // LDS atomics: lanes of a run of equal cells serialise on
                     // one address, which costs less here than merging the run
-                    const int cell = (int)__umul24((uint32_t)(iy - r0), (uint32_t)G) + ix;
+                    const int cell = (int)__umul24((uint32_t)ry, (uint32_t)G) + ix;
                     if (kHalf) atomicAdd(&tile[cell >> 1], 1u << ((cell & 1) << 4));
                     else atomicAdd(&tile[cell], 1u);
                 }
+            }
+        };
+        // samples [b, f) of indices below J, 64 per step: two register pairs
+        // of directions, step t uses one while step t + 1 is loaded into the
+        // other
+        auto walk = [&](int b, int f) {
+            float ca = 0.0f, sa = 0.0f, cb = 0.0f, sb = 0.0f;
+            if (b + lane < f) dir(b + lane, ca, sa);
+            for (int j0 = b; j0 < f; j0 += 128) {
+                const int ja = j0 + lane, jn = ja + 64, jm = ja + 128;
+                if (jn < f) dir(jn, cb, sb);
+                vote(ja < f, ca, sa);
+                if (j0 + 64 >= f) break;   // uniform
+                if (jm < f) dir(jm, ca, sa);
+                vote(jn < f, cb, sb);
             }
         };
         while (mask) {
             const int k = __builtin_ctzll(mask);
             const int e = k + __builtin_ctzll(~(mask >> k));   // bit 63 is never set
             mask &= ~(((1ull << (e - k)) - 1ull) << k);
-            const int jb = js + (k * L) / 63, je = js + (e * L) / 63;
-            // two register pairs of directions: step t uses one while step
-            // t + 1 is loaded into the other
-            float ca = 0.0f, sa = 0.0f, cb = 0.0f, sb = 0.0f;
-            if (jb + lane < je) dir(jb + lane, ca, sa);
-            for (int j0 = jb; j0 < je; j0 += 128) {
-                const int ja = j0 + lane, jn = ja + 64, jm = ja + 128;
-                if (jn < je) dir(jn, cb, sb);
-                vote(ja < je ? ja : -1, ca, sa);
-                if (j0 + 64 >= je) break;   // uniform
-                if (jm < je) dir(jm, ca, sa);
-                vote(jn < je ? jn : -1, cb, sb);
-            }
+            const int jb = js + (k * L) / 63, je = js + (e * L) / 63;   // js < J, je <= js + J
+            if (jb < J) walk(jb, je < J ? je : J);
+            if (je > J) walk(jb > J ? jb - J : 0, je - J);
         }
     }
 }

@@ -597,8 +597,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
             const bool up0 = f0 > 0.0f;
             const float y1 = yr + (up0 ? dy_up : dy_dn);
             const float f1 = vertex_F_fast(sc, tsa, tsb, nsc, xb, y1);
-            const bool clean = fabsf(lastf) > T;
-            if (clean && fabsf(f0) > T && fabsf(f1) > T) {
+            if (fabsf(lastf) > T && fabsf(f0) > T && fabsf(f1) > T) {
                 const bool up1 = f1 > 0.0f;
                 const int r1 = r + (up0 ? 1 : 0) - off;
                 const int r2 = r1 + (up1 ? 1 : 0) - off;
@@ -620,7 +619,7 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
                 x = xb;
                 // the state stays clean: lastf keeps a value beyond T
             } else {
-                step(clean, range0, pair0);
+                step(fabsf(lastf) > T, range0, pair0);
                 step(fabsf(lastf) > T, range1, pair1);
             }
         }
