@@ -1106,14 +1106,18 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
     const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
     // buffer resources over the direction tables (J floats each): one 32-bit
-    // offset per sample addresses both, and reads past the end return 0
+    // offset per sample addresses both, and reads past the end return 0, so
+    // the loads of a step are issued unconditionally (the wait for a step
+    // then counts exactly the loads issued after it)
     const __amdgpu_buffer_rsrc_t rcs = __builtin_amdgcn_make_buffer_rsrc((void*)I.scs, (short)0, 4 * J, 0x00020000);
     const __amdgpu_buffer_rsrc_t rsn = __builtin_amdgcn_make_buffer_rsrc((void*)I.ssn, (short)0, 4 * J, 0x00020000);
-    // direction j (0 <= j < J: a run that passes J is split there)
+    // direction j (a run that passes J is split there; j >= J only for
+    // samples that are not voted)
     auto dir = [&](int j, float& c, float& sn) {
         if (kLdsDirs) {
-            c = ldir[j];
-            sn = ldir[J + j];
+            const int jc = j < J ? j : J - 1;
+            c = ldir[jc];
+            sn = ldir[J + jc];
         } else {
             c = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rcs, j << 2, 0, 0));
             sn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsn, j << 2, 0, 0));
@@ -1164,19 +1168,23 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
                 }
             }
         };
-        // samples [b, f) of indices below J, 64 per step: two register pairs
-        // of directions, step t uses one while step t + 1 is loaded into the
-        // other
+        // samples [b, f) of indices below J, 64 per step: three register
+        // pairs of directions, step t uses one while steps t + 1 and t + 2
+        // are in flight in the others
         auto walk = [&](int b, int f) {
-            float ca = 0.0f, sa = 0.0f, cb = 0.0f, sb = 0.0f;
-            if (b + lane < f) dir(b + lane, ca, sa);
-            for (int j0 = b; j0 < f; j0 += 128) {
-                const int ja = j0 + lane, jn = ja + 64, jm = ja + 128;
-                if (jn < f) dir(jn, cb, sb);
-                vote(ja < f, ca, sa);
-                if (j0 + 64 >= f) break;   // uniform
-                if (jm < f) dir(jm, ca, sa);
-                vote(jn < f, cb, sb);
+            float c0, s0, c1, s1, c2, s2;
+            const int jl = b + lane;
+            dir(jl, c0, s0);
+            dir(jl + 64, c1, s1);
+            for (int j0 = jl; j0 - lane < f; j0 += 192) {
+                dir(j0 + 128, c2, s2);
+                vote(j0 < f, c0, s0);
+                if (j0 - lane + 64 >= f) break;   // uniform
+                dir(j0 + 192, c0, s0);
+                vote(j0 + 64 < f, c1, s1);
+                if (j0 - lane + 128 >= f) break;   // uniform
+                dir(j0 + 256, c1, s1);
+                vote(j0 + 128 < f, c2, s2);
             }
         };
         while (mask) {
