@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kVoteThreads) void k_vote(const ArcRecs R, const In
                 const bool live = li < nli;
                 int gn = 0;
                 if (lane == 0) gn = atomicAdd(&group_next, 64);
-                g0 = __shfl(gn, 0, 64);
+                g0 = __builtin_amdgcn_readlane(gn, 0);
                 if (g0 + lane < nli) pc_next = prange[base + g0 + lane];
                 // correspondences outside the walk's range of validity (column
                 // pass only): exhaustive cell test of the band by the whole wave
@@ -1140,15 +1140,19 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
             hn = rec[lane < 8 ? lane : 7];
             rn_row = reinterpret_cast<const int16_t*>(rec + 8)[lane];
         }
-        const uint32_t lw = __shfl(hw, 7);
+        // the record's words are uniform: read them into scalar registers
+        const uint32_t lw = __builtin_amdgcn_readlane(hw, 7);
         const int L = (int)(lw & 0x1FFFFu), M = (int)(lw >> 17);   // L <= 65536, M <= G + 4 <= 4100
         if (L == 0) continue;   // uniform
-        const float a1[3] = {__uint_as_float(__shfl(hw, 0)), __uint_as_float(__shfl(hw, 1)),
-                             __uint_as_float(__shfl(hw, 2))};
-        const float a2[3] = {__uint_as_float(__shfl(hw, 3)), __uint_as_float(__shfl(hw, 4)),
-                             __uint_as_float(__shfl(hw, 5))};
-        const int js = (int)__shfl(hw, 6);
-        const int rn = __shfl_down(rk, 1);
+        const float a1[3] = {__uint_as_float(__builtin_amdgcn_readlane(hw, 0)),
+                             __uint_as_float(__builtin_amdgcn_readlane(hw, 1)),
+                             __uint_as_float(__builtin_amdgcn_readlane(hw, 2))};
+        const float a2[3] = {__uint_as_float(__builtin_amdgcn_readlane(hw, 3)),
+                             __uint_as_float(__builtin_amdgcn_readlane(hw, 4)),
+                             __uint_as_float(__builtin_amdgcn_readlane(hw, 5))};
+        const int js = (int)__builtin_amdgcn_readlane(hw, 6);
+        // row of checkpoint lane + 1 (wavefront shift by one lane; lane 63 keeps its own)
+        const int rn = __builtin_amdgcn_update_dpp(rk, rk, 0x130, 0xf, 0xf, false);
         const int lo = (rk < rn ? rk : rn) - M, hi = (rk > rn ? rk : rn) + M;
         const int ck = (lane * L) / 63, cn = ((lane + 1) * L) / 63;
         const bool hit = lane < 63 && cn > ck && hi >= r0 && lo < r1;
