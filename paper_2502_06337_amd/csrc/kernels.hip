@@ -1028,6 +1028,10 @@ __device__ __forceinline__ float sample_row_coord(const float* a1, const float* 
     return ((s1 / (1.0f - s2)) + 1.0f) * hg;
 }
 
+// One lane per circle for the frame and window (its inputs are read
+// coalesced, and the slow parts of the frame run once per circle), then the
+// 64 checkpoint rows of each circle of the wave, one lane per checkpoint, from
+// the circle's values read into scalar registers.
 __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ P, const float* __restrict__ Q,
                                                       int64_t N, const Inst* __restrict__ insts,
                                                       const int4* __restrict__ items, uint32_t* __restrict__ recs) {
@@ -1038,57 +1042,67 @@ __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ 
     const int J = I.J, G = I.G;
     const float hg = 0.5f * (float)G;
     const float dth = 6.28318531f / (float)J;
-    for (int64_t li = wi.y + wave; li < wi.z; li += nw) {
-        const int64_t i = I.off + li;
-        uint32_t* rec = recs + (I.ssetup_off + li) * kSampleRec;
-        const float p[3] = {P[i], P[N + i], P[2 * N + i]};
-        const float q[3] = {Q[i], Q[N + i], Q[2 * N + i]};
+    for (int64_t base = wi.y + 64 * wave; base < wi.z; base += 64 * nw) {
+        const int64_t li = base + lane;
         float a1[3] = {0.0f, 0.0f, 0.0f}, a2[3] = {0.0f, 0.0f, 0.0f};
         int js = 0, L = 0, M = 0;
-        const bool ok = sample_frame(p, q, a1, a2);   // uniform
-        if (ok) {
-            // s_z = a1z cos t + a2z sin t is at most 0 on the half circle
-            // centred on t = atan2(a2z, a1z) + pi; within 0.01 of the equator
-            // plane every sample may be southern
-            const float rz2 = (a1[2] * a1[2]) + (a2[2] * a2[2]);
-            float scale = 1.0102f;   // bound on 1/(1 - s_z) over the window
-            bool all_rows = false;
-            if (rz2 < 1e-4f) {
-                js = 0;
-                L = J;
-            } else {
-                const float t0 = atan2f(a2[2], a1[2]) + 1.57079633f;   // start of the southern half
-                const int j0 = (int)ceilf((t0 + 3.14159265f) / dth) - 4;
-                L = (int)ceilf(3.14159265f / dth) + 9;
-                js = ((j0 % J) + J) % J;
-                // the window reaches 4.5 sample steps past the southern half
-                const float sm = sqrtf(rz2) * sinf(fminf(4.5f * dth, 1.57079633f));
-                if (L >= J || sm > 0.5f) {   // few samples: walk the whole circle in every band
+        if (li < wi.z) {
+            const int64_t i = I.off + li;
+            const float p[3] = {P[i], P[N + i], P[2 * N + i]};
+            const float q[3] = {Q[i], Q[N + i], Q[2 * N + i]};
+            if (sample_frame(p, q, a1, a2)) {
+                // s_z = a1z cos t + a2z sin t is at most 0 on the half circle
+                // centred on t = atan2(a2z, a1z) + pi; within 0.01 of the
+                // equator plane every sample may be southern
+                const float rz2 = (a1[2] * a1[2]) + (a2[2] * a2[2]);
+                float scale = 1.0102f;   // bound on 1/(1 - s_z) over the window
+                bool all_rows = false;
+                if (rz2 < 1e-4f) {
                     js = 0;
                     L = J;
-                    all_rows = true;
                 } else {
-                    scale = 1.0f / (1.0f - sm);
+                    const float t0 = atan2f(a2[2], a1[2]) + 1.57079633f;   // start of the southern half
+                    const int j0 = (int)ceilf((t0 + 3.14159265f) / dth) - 4;
+                    L = (int)ceilf(3.14159265f / dth) + 9;
+                    js = ((j0 % J) + J) % J;
+                    // the window reaches 4.5 sample steps past the southern half
+                    const float sm = sqrtf(rz2) * sinf(fminf(4.5f * dth, 1.57079633f));
+                    if (L >= J || sm > 0.5f) {   // few samples: walk the whole circle in every band
+                        js = 0;
+                        L = J;
+                        all_rows = true;
+                    } else {
+                        scale = 1.0f / (1.0f - sm);
+                    }
                 }
+                const float l = dth * ((float)L / 63.0f + 1.0f) * scale * 1.01f;
+                // stored rows lie in [-2, G + 1], so a margin of G + 4 reaches every row
+                M = all_rows ? G + 4 : (int)ceilf(fminf(l * l * 0.125f * hg + 0.05f, (float)G)) + 1;
+                M = M < G + 4 ? M : G + 4;
             }
-            const float l = dth * ((float)L / 63.0f + 1.0f) * scale * 1.01f;
-            // stored rows lie in [-2, G + 1], so a margin of G + 4 reaches every row
-            M = all_rows ? G + 4 : (int)ceilf(fminf(l * l * 0.125f * hg + 0.05f, (float)G)) + 1;
-            M = M < G + 4 ? M : G + 4;
+            // header: the frame, js, L | M << 17 (L = 0: no samples)
+            uint32_t* rec = recs + (I.ssetup_off + li) * kSampleRec;
+            for (int k = 0; k < 3; ++k) {
+                rec[k] = __float_as_uint(a1[k]);
+                rec[3 + k] = __float_as_uint(a2[k]);
+            }
+            rec[6] = (uint32_t)js;
+            rec[7] = (uint32_t)L | ((uint32_t)M << 17);
         }
-        if (lane < 8) {
-            const float f = lane == 0 ? a1[0] : lane == 1 ? a1[1] : lane == 2 ? a1[2]
-                          : lane == 3 ? a2[0] : lane == 4 ? a2[1] : a2[2];
-            rec[lane] = lane < 6 ? __float_as_uint(f)
-                                 : (lane == 6 ? (uint32_t)js : ((uint32_t)L | ((uint32_t)M << 17)));
+        const int ncirc = wi.z - base < 64 ? (int)(wi.z - base) : 64;
+        for (int k = 0; k < ncirc; ++k) {
+            const int Lk = __builtin_amdgcn_readlane(L, k);
+            if (Lk == 0) continue;   // uniform
+            auto bcast = [k](float v) { return __uint_as_float(__builtin_amdgcn_readlane(__float_as_uint(v), k)); };
+            const float b1[3] = {bcast(a1[0]), bcast(a1[1]), bcast(a1[2])};
+            const float b2[3] = {bcast(a2[0]), bcast(a2[1]), bcast(a2[2])};
+            int c = __builtin_amdgcn_readlane(js, k) + (lane * Lk) / 63;
+            if (c >= J) c -= J;
+            float t = sample_row_coord(b1, b2, I.scs[c], I.ssn[c], hg);
+            t = fminf(fmaxf(t, -2.0f), (float)(G + 1));   // also maps NaN to -2
+            const int r = (int)floorf(t);
+            reinterpret_cast<int16_t*>(recs + (I.ssetup_off + base + k) * kSampleRec + 8)[lane] = (int16_t)r;
         }
-        if (!ok) continue;
-        int c = js + (lane * L) / 63;
-        if (c >= J) c -= J;
-        float t = sample_row_coord(a1, a2, I.scs[c], I.ssn[c], hg);
-        t = fminf(fmaxf(t, -2.0f), (float)(G + 1));   // also maps NaN to -2
-        const int r = (int)floorf(t);
-        reinterpret_cast<int16_t*>(rec + 8)[lane] = (int16_t)r;
     }
 }
 
