@@ -1117,43 +1117,49 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
                                                  const float* ldir, uint32_t* tile, int r0, int r1) {
     const int G = I.G, J = I.J;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    // the wave index is uniform: say so, so that the circle index and the
+    // record offsets live in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
-    // buffer resources over the direction tables (J floats each): one 32-bit
-    // offset per sample addresses both, and reads past the end return 0, so
-    // the loads of a step are issued unconditionally (the wait for a step
-    // then counts exactly the loads issued after it)
+    // buffer resources over the direction tables (J floats each) and over the
+    // instance's circle records; reads past the end return 0, so the loads of
+    // a step are issued unconditionally (the wait for a step then counts
+    // exactly the loads issued after it)
     const __amdgpu_buffer_rsrc_t rcs = __builtin_amdgcn_make_buffer_rsrc((void*)I.scs, (short)0, 4 * J, 0x00020000);
     const __amdgpu_buffer_rsrc_t rsn = __builtin_amdgcn_make_buffer_rsrc((void*)I.ssn, (short)0, 4 * J, 0x00020000);
-    // direction j (a run that passes J is split there; j >= J only for
-    // samples that are not voted)
-    auto dir = [&](int j, float& c, float& sn) {
+    const __amdgpu_buffer_rsrc_t rrec = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(recs + I.ssetup_off * kSampleRec), (short)0, I.n * kSampleRec * 4, 0x00020000);
+    const int lane4 = lane << 2;
+    // directions jb + lane (a run that passes J is split there; indices past
+    // J belong to samples that are not voted)
+    auto dir = [&](int jb, float& c, float& sn) {
         if (kLdsDirs) {
-            const int jc = j < J ? j : J - 1;
+            const int jc = jb + lane < J ? jb + lane : J - 1;
             c = ldir[jc];
             sn = ldir[J + jc];
         } else {
-            c = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rcs, j << 2, 0, 0));
-            sn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsn, j << 2, 0, 0));
+            const int off = lane4 + (jb << 2);
+            c = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rcs, off, 0, 0));
+            sn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsn, off, 0, 0));
         }
+    };
+    // circle li's record: lanes 0..7 take the header words, every lane its
+    // checkpoint row (the scalar offset carries the circle)
+    const int hoff = (lane < 8 ? lane : 7) << 2, roff = 32 + (lane << 1);
+    auto load_rec = [&](int64_t li, uint32_t& h, int& row) {
+        const int base = __builtin_amdgcn_readfirstlane((int)li * (kSampleRec * 4));   // uniform
+        h = __builtin_amdgcn_raw_buffer_load_b32(rrec, hoff, base, 0);
+        row = (int)(int16_t)__builtin_amdgcn_raw_buffer_load_b16(rrec, roff, base, 0);
     };
     // the next circle's record is loaded while the current one is walked
     int64_t li = wi.z + wave;
     uint32_t hn = 0u;
     int rn_row = 0;
-    if (li < wi.w) {
-        const uint32_t* rec = recs + (I.ssetup_off + li) * kSampleRec;
-        hn = rec[lane < 8 ? lane : 7];
-        rn_row = reinterpret_cast<const int16_t*>(rec + 8)[lane];
-    }
+    if (li < wi.w) load_rec(li, hn, rn_row);
     for (; li < wi.w; li += nw) {
         const uint32_t hw = hn;
         const int rk = rn_row;
-        if (li + nw < wi.w) {
-            const uint32_t* rec = recs + (I.ssetup_off + li + nw) * kSampleRec;
-            hn = rec[lane < 8 ? lane : 7];
-            rn_row = reinterpret_cast<const int16_t*>(rec + 8)[lane];
-        }
+        if (li + nw < wi.w) load_rec(li + nw, hn, rn_row);
         // the record's words are uniform: read them into scalar registers
         const uint32_t lw = __builtin_amdgcn_readlane(hw, 7);
         const int L = (int)(lw & 0x1FFFFu), M = (int)(lw >> 17);   // L <= 65536, M <= G + 4 <= 4100
@@ -1165,10 +1171,13 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
                              __uint_as_float(__builtin_amdgcn_readlane(hw, 4)),
                              __uint_as_float(__builtin_amdgcn_readlane(hw, 5))};
         const int js = (int)__builtin_amdgcn_readlane(hw, 6);
-        // row of checkpoint lane + 1 (wavefront shift by one lane; lane 63 keeps its own)
+        // row and first sample of checkpoint lane + 1 (wavefront shift by one
+        // lane; lane 63 keeps its own)
         const int rn = __builtin_amdgcn_update_dpp(rk, rk, 0x130, 0xf, 0xf, false);
+        // (lane L) / 63 for lane L < 2^22: multiply-high by ceil(2^37 / 63)
+        const int ck = (int)(__umulhi(__umul24((uint32_t)lane, (uint32_t)L), 2181570691u) >> 5);
+        const int cn = __builtin_amdgcn_update_dpp(ck, ck, 0x130, 0xf, 0xf, false);
         const int lo = (rk < rn ? rk : rn) - M, hi = (rk > rn ? rk : rn) + M;
-        const int ck = (lane * L) / 63, cn = ((lane + 1) * L) / 63;
         const bool hit = lane < 63 && cn > ck && hi >= r0 && lo < r1;
         unsigned long long mask = __ballot(hit);
         // one sample: its cell in the band tile, or nothing
@@ -1186,23 +1195,22 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
                 }
             }
         };
-        // samples [b, f) of indices below J, 64 per step: three register
-        // pairs of directions, step t uses one while steps t + 1 and t + 2
-        // are in flight in the others
+        // samples [b, f) of indices below J, 64 per step from the uniform
+        // base j0: three register pairs of directions, step t uses one while
+        // steps t + 1 and t + 2 are in flight in the others
         auto walk = [&](int b, int f) {
             float c0, s0, c1, s1, c2, s2;
-            const int jl = b + lane;
-            dir(jl, c0, s0);
-            dir(jl + 64, c1, s1);
-            for (int j0 = jl; j0 - lane < f; j0 += 192) {
+            dir(b, c0, s0);
+            dir(b + 64, c1, s1);
+            for (int j0 = b; j0 < f; j0 += 192) {
                 dir(j0 + 128, c2, s2);
-                vote(j0 < f, c0, s0);
-                if (j0 - lane + 64 >= f) break;   // uniform
+                vote(lane < f - j0, c0, s0);
+                if (j0 + 64 >= f) break;   // uniform
                 dir(j0 + 192, c0, s0);
-                vote(j0 + 64 < f, c1, s1);
-                if (j0 - lane + 128 >= f) break;   // uniform
+                vote(lane < f - j0 - 64, c1, s1);
+                if (j0 + 128 >= f) break;   // uniform
                 dir(j0 + 256, c1, s1);
-                vote(j0 + 128 < f, c2, s2);
+                vote(lane < f - j0 - 128, c2, s2);
             }
         };
         while (mask) {
