@@ -1182,17 +1182,27 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
         unsigned long long mask = __ballot(hit);
         // one sample: its cell in the band tile, or nothing
         const unsigned rows = (unsigned)(r1 - r0);
+        // Without branches: every lane evaluates the rule (a northern sample's
+        // values are garbage and unused) and adds to the tile, 0 when the
+        // sample is not voted in this band (to its own word lane).  LDS
+        // atomics: lanes of a run of equal cells serialise on one address,
+        // which costs less here than merging the run.
         auto vote = [&](bool valid, float c, float sn) {
-            int ix, iy;
-            if (valid && sample_cell(a1, a2, c, sn, G, hg, ix, iy)) {
-                const int ry = iy - r0;
-                if ((unsigned)ry < rows) {
-                    // LDS atomics: lanes of a run of equal cells serialise on
-                    // one address, which costs less here than merging the run
-                    const int cell = (int)__umul24((uint32_t)ry, (uint32_t)G) + ix;
-                    if (kHalf) atomicAdd(&tile[cell >> 1], 1u << ((cell & 1) << 4));
-                    else atomicAdd(&tile[cell], 1u);
-                }
+            const float s0 = (a1[0] * c) + (a2[0] * sn);
+            const float s1 = (a1[1] * c) + (a2[1] * sn);
+            const float s2 = (a1[2] * c) + (a2[2] * sn);
+            const float rinv = recip_1_4(1.0f - s2);
+            const float u = s0 * rinv, v = s1 * rinv;
+            const int ix = clamp_int(floor_to_int(__builtin_fmaf(u, hg, hg)), G - 1);
+            const int iy = clamp_int(floor_to_int(__builtin_fmaf(v, hg, hg)), G - 1);
+            const int ry = iy - r0;
+            const bool ok = valid && s2 <= 0.0f && (unsigned)ry < rows;
+            const int cell = (int)__umul24((uint32_t)ry, (uint32_t)G) + ix;
+            if (kHalf) {
+                const uint32_t inc = 1u << ((cell & 1) << 4);
+                atomicAdd(&tile[ok ? cell >> 1 : lane], ok ? inc : 0u);
+            } else {
+                atomicAdd(&tile[ok ? cell : lane], ok ? 1u : 0u);
             }
         };
         // samples [b, f) of indices below J, 64 per step from the uniform
