@@ -1121,6 +1121,7 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
     // record offsets live in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
+    const int tw = (kHalf ? G >> 1 : G) + 1;   // words per tile row (odd: rows start in different banks)
     // buffer resources over the direction tables (J floats each) and over the
     // instance's circle records; reads past the end return 0, so the loads of
     // a step are issued unconditionally (the wait for a step then counts
@@ -1197,12 +1198,15 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
             const int iy = clamp_int(floor_to_int(__builtin_fmaf(v, hg, hg)), G - 1);
             const int ry = iy - r0;
             const bool ok = valid && s2 <= 0.0f && (unsigned)ry < rows;
-            const int cell = (int)__umul24((uint32_t)ry, (uint32_t)G) + ix;
+            // tile rows of tw words: G/2 (+1 pad) with 16-bit counters, cells
+            // 2m and 2m + 1 of a row in word m; G (+1) with 32-bit ones
             if (kHalf) {
-                const uint32_t inc = 1u << ((cell & 1) << 4);
-                atomicAdd(&tile[ok ? cell >> 1 : lane], ok ? inc : 0u);
+                const int word = (int)__umul24((uint32_t)ry, (uint32_t)tw) + (ix >> 1);
+                const uint32_t inc = 1u << ((ix & 1) << 4);
+                atomicAdd(&tile[ok ? word : lane], ok ? inc : 0u);
             } else {
-                atomicAdd(&tile[ok ? cell : lane], ok ? 1u : 0u);
+                const int word = (int)__umul24((uint32_t)ry, (uint32_t)tw) + ix;
+                atomicAdd(&tile[ok ? word : lane], ok ? 1u : 0u);
             }
         };
         // samples [b, f) of indices below J, 64 per step from the uniform
@@ -1252,11 +1256,15 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
     const int cells = bw * G;
     const bool half = I.shalf != 0;   // 16-bit counters: cells 2m and 2m + 1 share word m
     const int words = half ? cells >> 1 : cells;
+    // the tile's rows carry one pad word each (an odd stride spreads the
+    // cells of one column over the LDS banks)
+    const int lrw = half ? 30 - __clz(G) : 31 - __clz(G);   // log2 of the words of a row
+    const int padded = words + bw;
     // LDS: the sample directions (when they fit), then the band tile
     const bool lds_dirs = I.sdir_lds != 0;
     float* ldir = reinterpret_cast<float*>(sm);
     uint32_t* tile = sm + (lds_dirs ? 2 * J : 0);
-    for (int e = threadIdx.x; e < words; e += blockDim.x) tile[e] = 0u;
+    for (int e = threadIdx.x; e < padded; e += blockDim.x) tile[e] = 0u;
     if (lds_dirs)
         for (int e = threadIdx.x; e < J; e += blockDim.x) {
             ldir[e] = I.scs[e];
@@ -1273,7 +1281,7 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
     __syncthreads();
     const int chunk = wi.z / I.schunk;
     uint32_t* dst = part + I.spart_off + ((int64_t)chunk * I.snb + band) * words;
-    for (int e = threadIdx.x; e < words; e += blockDim.x) dst[e] = tile[e];
+    for (int e = threadIdx.x; e < words; e += blockDim.x) dst[e] = tile[e + (e >> lrw)];
 }
 
 // grid cell = sum over the instance's circle chunks of its band slot.  With
@@ -1943,8 +1951,9 @@ SampleLayout sample_plan(int G, int J, int64_t n) {
             L.bw = (int)(cells / G);
             L.chunk = ch;
             L.part_words = nch * (GG / 2);
-            L.dirs_lds = (size_t)cells * 2 + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
-            L.lds_bytes = (size_t)cells * 2 + (L.dirs_lds ? (size_t)J * 8 : 0);
+            const size_t tile = (size_t)cells * 2 + (size_t)(cells / G) * 4;   // + one pad word per row
+            L.dirs_lds = tile + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
+            L.lds_bytes = tile + (L.dirs_lds ? (size_t)J * 8 : 0);
             return L;
         }
     }
@@ -1958,8 +1967,9 @@ SampleLayout sample_plan(int G, int J, int64_t n) {
     L.bw = (int)(cells / G);
     L.chunk = ch;
     L.part_words = (n > 0 ? (n + ch - 1) / ch : 0) * GG;
-    L.dirs_lds = (size_t)cells * 4 + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
-    L.lds_bytes = (size_t)cells * 4 + (L.dirs_lds ? (size_t)J * 8 : 0);
+    const size_t tile = (size_t)cells * 4 + (size_t)(cells / G) * 4;   // + one pad word per row
+    L.dirs_lds = tile + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
+    L.lds_bytes = tile + (L.dirs_lds ? (size_t)J * 8 : 0);
     return L;
 }
 
