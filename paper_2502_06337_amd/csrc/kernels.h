@@ -167,6 +167,7 @@ void launch_fine_peak(const uint32_t* fine_arena, const Inst* insts, int ninst, 
 constexpr int kSampleTile = 32768;    // u32 counters per band tile (128 KiB of LDS), or the whole grid if smaller
 constexpr int kSampleRec = 40;        // u32 words per circle record
 constexpr int kSampleSetupChunk = 1024;
+constexpr int kSetupLdsDirs = 8192;   // sample counts J whose direction tables the setup stages in LDS
 // Layout of the sampling band pass for an instance of n circles: band tile
 // rows (a power of two), 16-bit counters (two per word) where the per-item
 // count bound allows it, else 32-bit, circles per band item, partial arena

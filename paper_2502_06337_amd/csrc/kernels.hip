@@ -1035,6 +1035,7 @@ __device__ __forceinline__ float sample_row_coord(const float* a1, const float* 
 __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ P, const float* __restrict__ Q,
                                                       int64_t N, const Inst* __restrict__ insts,
                                                       const int4* __restrict__ items, uint32_t* __restrict__ recs) {
+    extern __shared__ __align__(16) float sdir[];
     const int4 wi = items[blockIdx.x];
     const Inst& I = insts[wi.x];
     const int lane = threadIdx.x & 63;
@@ -1042,6 +1043,18 @@ __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ 
     const int J = I.J, G = I.G;
     const float hg = 0.5f * (float)G;
     const float dth = 6.28318531f / (float)J;
+    // the 64 checkpoints of a circle read directions far apart: from LDS when
+    // the tables fit (J <= kSetupLdsDirs), else from global memory
+    const bool lds = J <= kSetupLdsDirs;
+    if (lds) {
+        for (int e = threadIdx.x; e < J; e += blockDim.x) {
+            sdir[e] = I.scs[e];
+            sdir[J + e] = I.ssn[e];
+        }
+        __syncthreads();
+    }
+    const float* dcs = lds ? sdir : I.scs;
+    const float* dsn = lds ? sdir + J : I.ssn;
     for (int64_t base = wi.y + 64 * wave; base < wi.z; base += 64 * nw) {
         const int64_t li = base + lane;
         float a1[3] = {0.0f, 0.0f, 0.0f}, a2[3] = {0.0f, 0.0f, 0.0f};
@@ -1098,7 +1111,7 @@ __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ 
             const float b2[3] = {bcast(a2[0]), bcast(a2[1]), bcast(a2[2])};
             int c = __builtin_amdgcn_readlane(js, k) + (lane * Lk) / 63;
             if (c >= J) c -= J;
-            float t = sample_row_coord(b1, b2, I.scs[c], I.ssn[c], hg);
+            float t = sample_row_coord(b1, b2, dcs[c], dsn[c], hg);
             t = fminf(fmaxf(t, -2.0f), (float)(G + 1));   // also maps NaN to -2
             const int r = (int)floorf(t);
             reinterpret_cast<int16_t*>(recs + (I.ssetup_off + base + k) * kSampleRec + 8)[lane] = (int16_t)r;
@@ -1122,12 +1135,14 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
     const int tw = (kHalf ? G >> 1 : G) + 1;   // words per tile row (odd: rows start in different banks)
-    // buffer resources over the direction tables (J floats each) and over the
-    // instance's circle records; reads past the end return 0, so the loads of
-    // a step are issued unconditionally (the wait for a step then counts
-    // exactly the loads issued after it)
-    const __amdgpu_buffer_rsrc_t rcs = __builtin_amdgcn_make_buffer_rsrc((void*)I.scs, (short)0, 4 * J, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rsn = __builtin_amdgcn_make_buffer_rsrc((void*)I.ssn, (short)0, 4 * J, 0x00020000);
+    // buffer resources over the direction tables and over the instance's
+    // circle records; reads past the end return 0, so the loads of a step are
+    // issued unconditionally (the wait for a step then counts exactly the
+    // loads issued after it)
+    // one resource over both direction tables: the sines follow the cosines
+    // (I.ssn = I.scs + J), reached through a scalar offset of 4 J bytes
+    const __amdgpu_buffer_rsrc_t rdir = __builtin_amdgcn_make_buffer_rsrc((void*)I.scs, (short)0, 8 * J, 0x00020000);
+    const int sn_off = 4 * J;
     const __amdgpu_buffer_rsrc_t rrec = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(recs + I.ssetup_off * kSampleRec), (short)0, I.n * kSampleRec * 4, 0x00020000);
     const int lane4 = lane << 2;
@@ -1139,9 +1154,10 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
             c = ldir[jc];
             sn = ldir[J + jc];
         } else {
+            // offsets past J * 4 (not voted) read sines or, past 8 J, zeros
             const int off = lane4 + (jb << 2);
-            c = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rcs, off, 0, 0));
-            sn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsn, off, 0, 0));
+            c = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rdir, off, 0, 0));
+            sn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rdir, off, sn_off, 0));
         }
     };
     // circle li's record: lanes 0..7 take the header words, every lane its
@@ -1857,6 +1873,7 @@ void init_kernel_attributes() {
     set_lds_limit((const void*)k_angle_hist);
     set_lds_limit((const void*)k_angle_fine_hist);
     set_lds_limit((const void*)k_sample_vote);
+    set_lds_limit((const void*)k_sample_setup);
 }
 
 void launch_zero_list(const ZeroList& zl, hipStream_t s) {
@@ -1977,7 +1994,11 @@ void launch_sample_vote(const float* P, const float* Q, int64_t N, const Inst* i
                         int nsetup, const int4* band_items, int nband, const int4* cell_items, int ncell,
                         uint32_t* recs, uint32_t* part, uint32_t* grid_arena, size_t lds_bytes, hipStream_t s) {
     if (nband <= 0) return;
-    hipLaunchKernelGGL(k_sample_setup, dim3((unsigned)nsetup), dim3(256), 0, s, P, Q, N, insts, setup_items, recs);
+    // room for the direction tables of the largest J staged in LDS (instances
+    // with a larger J read them from global memory)
+    const size_t setup_lds = (size_t)kSetupLdsDirs * 2 * sizeof(float);
+    hipLaunchKernelGGL(k_sample_setup, dim3((unsigned)nsetup), dim3(256), setup_lds, s, P, Q, N, insts, setup_items,
+                       recs);
     hipLaunchKernelGGL(k_sample_vote, dim3((unsigned)nband), dim3(1024), lds_bytes, s, insts, band_items, recs, part);
     hipLaunchKernelGGL(k_sample_reduce, dim3((unsigned)ncell, 32), dim3(256), 0, s, insts, cell_items, part,
                        grid_arena);
