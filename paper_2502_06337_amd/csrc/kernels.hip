@@ -1132,7 +1132,9 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
     const int lane = threadIdx.x & 63;
     // the wave index is uniform: say so, so that the circle index and the
     // record offsets live in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    __asm__("" : "+s"(wave));   // kept in a scalar register (not recomputed inside the loops)
+    const int nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
     const int tw = (kHalf ? G >> 1 : G) + 1;   // words per tile row (odd: rows start in different banks)
     // buffer resources over the direction tables and over the instance's
@@ -1219,10 +1221,10 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
             if (kHalf) {
                 const int word = (int)__umul24((uint32_t)ry, (uint32_t)tw) + (ix >> 1);
                 const uint32_t inc = 1u << ((ix & 1) << 4);
-                atomicAdd(&tile[ok ? word : lane], ok ? inc : 0u);
+                if (ok) atomicAdd(&tile[word], inc);
             } else {
                 const int word = (int)__umul24((uint32_t)ry, (uint32_t)tw) + ix;
-                atomicAdd(&tile[ok ? word : lane], ok ? 1u : 0u);
+                if (ok) atomicAdd(&tile[word], 1u);
             }
         };
         // samples [b, f) of indices below J, 64 per step from the uniform
