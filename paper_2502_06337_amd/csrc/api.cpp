@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <limits>
 #include <memory>
 #include <vector>
 
@@ -122,26 +123,33 @@ hipStream_t internal_stream(DeviceCtx* ctx) {
 
 // Angle tables: boundary k at phi_k = -pi + k * (2 pi / B) and bin centres
 // -pi + (k + 1/2) (2 pi / B), evaluated in double and rounded once to float.
+// Layout: cos, kDirPad NaNs, sin, kDirPad NaNs, centre angle, cos, sin.
+size_t angle_table_floats(int B) { return 5 * (size_t)B + 2 * kDirPad; }
+
 void fill_angle_tables(float* h, int B) {
     const double step = (2.0 * M_PI) / (double)B;
+    float* hc = h;
+    float* hs = h + B + kDirPad;
+    float* hr = hs + B + kDirPad;
     for (int k = 0; k < B; ++k) {
         double phi = -M_PI + (double)k * step;
-        h[k] = (float)std::cos(phi);
-        h[B + k] = (float)std::sin(phi);
+        hc[k] = (float)std::cos(phi);
+        hs[k] = (float)std::sin(phi);
         double ph = -M_PI + ((double)k + 0.5) * step;
-        h[2 * B + k] = (float)ph;
-        h[3 * B + k] = (float)std::cos(ph);
-        h[4 * B + k] = (float)std::sin(ph);
+        hr[k] = (float)ph;
+        hr[B + k] = (float)std::cos(ph);
+        hr[2 * B + k] = (float)std::sin(ph);
     }
+    for (int k = 0; k < kDirPad; ++k) hc[B + k] = hs[B + k] = std::numeric_limits<float>::quiet_NaN();
 }
 
 static AngleTables split_angle_tables(float* d, int B) {
     AngleTables t;
     t.tc = d;
-    t.ts = d + B;
-    t.th = d + 2 * B;
-    t.ct = d + 3 * B;
-    t.st = d + 4 * B;
+    t.ts = d + B + kDirPad;
+    t.th = t.ts + B + kDirPad;
+    t.ct = t.th + B;
+    t.st = t.th + 2 * B;
     return t;
 }
 
@@ -149,7 +157,7 @@ const AngleTables* angle_tables(DeviceCtx* ctx, int B) {
     std::lock_guard<std::mutex> lk(ctx->table_mu);
     auto it = ctx->angle.find(B);
     if (it != ctx->angle.end()) return &it->second;
-    std::vector<float> h(5 * (size_t)B);
+    std::vector<float> h(angle_table_floats(B));
     fill_angle_tables(h.data(), B);
     float* d = nullptr;
     if (hipMalloc((void**)&d, h.size() * sizeof(float)) != hipSuccess) return nullptr;
@@ -197,7 +205,7 @@ const int16_t* disk_table(DeviceCtx* ctx, int G) {
 const AngleTables* TableSink::angle_tables(int B) {
     for (int i = 0; i < nangle; ++i)
         if (angle_B[i] == B) return &angle[i];
-    const size_t bytes = (5 * (size_t)B * sizeof(float) + 255) / 256 * 256;
+    const size_t bytes = (angle_table_floats(B) * sizeof(float) + 255) / 256 * 256;
     if (nangle == 4 || used + bytes > cap) return nullptr;
     fill_angle_tables(reinterpret_cast<float*>(host + used), B);
     angle_B[nangle] = B;

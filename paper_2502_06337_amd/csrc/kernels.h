@@ -19,6 +19,10 @@ constexpr uint32_t kFlagLine = 4u;        // c == 0: the projected curve is a li
 constexpr uint32_t kFlagLineDown = 8u;    // line whose cross coordinate decreases along the scan
 
 constexpr int kMaxPeaks = 8;
+// NaN entries after the cosine and the sine table of every angle table
+// (B = J for the sampling rule's directions): a sample index in [J, J + 64)
+// reads NaN, so its s_z <= 0 test fails
+constexpr int kDirPad = 64;
 // A coarse LDS band tile holds 16-bit counters, two per u32 word: the cells
 // (j, k) and (j + 1, k) of an even/odd pair of cell lines share a word.  A
 // counter takes at most one vote per correspondence of its work item, so items
@@ -79,8 +83,8 @@ struct Inst {
     const float* fst;
     int32_t rule;         // coarse accumulator rule: 0 per-cell rule, 1 literal sampling rule
     int32_t J;            // samples per great circle (rule 1)
-    const float* scs;     // sample directions: cos, sin of -pi + j 2pi/J (rule 1)
-    const float* ssn;
+    const float* scs;     // sample directions: cos, sin of -pi + j 2pi/J (rule 1); each
+    const float* ssn;     // table is followed by kDirPad NaNs, ssn = scs + J + kDirPad
     int32_t sbw, snb;     // rule 1: rows per band tile, bands
     int32_t sdir_lds;     // rule 1: sample directions staged in LDS
     int32_t shalf;        // rule 1: 16-bit band counters (partial tiles hold two per word)

@@ -1125,6 +1125,12 @@ __global__ __launch_bounds__(256) void k_sample_setup(const float* __restrict__ 
 // in word m.  Each wave walks 64 samples per step with the exact per-sample
 // cell; the directions of the next step are loaded into the other of two
 // register pairs while this step is evaluated.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;   // a word of LDS
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
+
 template <bool kLdsDirs, bool kHalf>
 __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, const uint32_t* __restrict__ recs,
                                                  const float* ldir, uint32_t* tile, int r0, int r1) {
@@ -1137,14 +1143,18 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
     const int nw = blockDim.x >> 6;
     const float hg = 0.5f * (float)G;
     const int tw = (kHalf ? G >> 1 : G) + 1;   // words per tile row (odd: rows start in different banks)
+    const uint32_t tw4 = 4u * (uint32_t)tw;
+    const uint32_t tb = (uint32_t)(uintptr_t)(lds_u32*)tile;   // LDS address of the tile
     // buffer resources over the direction tables and over the instance's
     // circle records; reads past the end return 0, so the loads of a step are
     // issued unconditionally (the wait for a step then counts exactly the
     // loads issued after it)
     // one resource over both direction tables: the sines follow the cosines
-    // (I.ssn = I.scs + J), reached through a scalar offset of 4 J bytes
-    const __amdgpu_buffer_rsrc_t rdir = __builtin_amdgcn_make_buffer_rsrc((void*)I.scs, (short)0, 8 * J, 0x00020000);
-    const int sn_off = 4 * J;
+    // and their pads (I.ssn = I.scs + J + kDirPad), reached through a scalar
+    // offset of 4 (J + kDirPad) bytes
+    const __amdgpu_buffer_rsrc_t rdir =
+        __builtin_amdgcn_make_buffer_rsrc((void*)I.scs, (short)0, 8 * (J + kDirPad), 0x00020000);
+    const int sn_off = 4 * (J + kDirPad);
     const __amdgpu_buffer_rsrc_t rrec = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(recs + I.ssetup_off * kSampleRec), (short)0, I.n * kSampleRec * 4, 0x00020000);
     const int lane4 = lane << 2;
@@ -1156,7 +1166,8 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
             c = ldir[jc];
             sn = ldir[J + jc];
         } else {
-            // offsets past J * 4 (not voted) read sines or, past 8 J, zeros
+            // indices J..J+63 read NaN pads (never voted), beyond them sines
+            // or zeros (loads of a step past the run, not used)
             const int off = lane4 + (jb << 2);
             c = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rdir, off, 0, 0));
             sn = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rdir, off, sn_off, 0));
@@ -1212,17 +1223,33 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
             const float s2 = (a1[2] * c) + (a2[2] * sn);
             const float rinv = recip_1_4(1.0f - s2);
             const float u = s0 * rinv, v = s1 * rinv;
-            const int ix = clamp_int(floor_to_int(__builtin_fmaf(u, hg, hg)), G - 1);
+            const int ixf = floor_to_int(__builtin_fmaf(u, hg, hg));
             const int iy = clamp_int(floor_to_int(__builtin_fmaf(v, hg, hg)), G - 1);
             const int ry = iy - r0;
             const bool ok = valid && s2 <= 0.0f && (unsigned)ry < rows;
             // tile rows of tw words: G/2 (+1 pad) with 16-bit counters, cells
             // 2m and 2m + 1 of a row in word m; G (+1) with 32-bit ones
             if (kHalf) {
-                const int word = (int)__umul24((uint32_t)ry, (uint32_t)tw) + (ix >> 1);
-                const uint32_t inc = 1u << ((ix & 1) << 4);
-                if (ok) atomicAdd(&tile[word], inc);
+                // The column is not clamped here.  A voted sample has s_z <= 0,
+                // and the frame and the directions are unit vectors to a few
+                // ulps, so |u| <= 1 + 2^-16 and ixf lies in [-1, G] (G <= 4096).
+                // Cell G of row r lands in the low half of the row's pad word,
+                // cell -1 in the high half of the word before the row (the pad
+                // of row r - 1, or a word before the tile); the tile store adds
+                // them to cells G - 1 and 0, which is the rule's clamp.
+                // LDS address tb + ry (4 tw) + 4 (ixf >> 1) = tb + 2 (ixf & ~1) + ry (4 tw)
+                // in three instructions (a garbage ry of an unvoted lane is
+                // never used)
+                uint32_t addr;
+                __asm__("v_and_b32 %0, -2, %1\n\tv_lshl_add_u32 %0, %0, 1, %2\n\tv_mad_u32_u24 %0, %3, %4, %0"
+                        : "=&v"(addr)
+                        : "v"(ixf), "s"(tb), "v"(ry), "s"(tw4));
+                const uint32_t inc = 1u << ((ixf & 1) << 4);
+                if (ok)
+                    __hip_atomic_fetch_add((lds_u32*)(uintptr_t)addr, inc, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
             } else {
+                const int ix = clamp_int(ixf, G - 1);
                 const int word = (int)__umul24((uint32_t)ry, (uint32_t)tw) + ix;
                 if (ok) atomicAdd(&tile[word], 1u);
             }
@@ -1230,29 +1257,43 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
         // samples [b, f) of indices below J, 64 per step from the uniform
         // base j0: three register pairs of directions, step t uses one while
         // steps t + 1 and t + 2 are in flight in the others
-        auto walk = [&](int b, int f) {
+        // Checked: lanes past f are not voted.  Unchecked: the last step's
+        // lanes past f are evaluated too, which is exact when (a) checkpoint
+        // intervals hold at least 64 samples, so the up to 63 samples past a
+        // run's end lie in the interval after it, which reaches no row of the
+        // band (else it would be part of the run) or lies outside the window,
+        // where every sample is northern (L + 64 <= J, or the window is the
+        // whole circle), and (b) indices J..J+62 read the tables' NaN pads, so
+        // s_z <= 0 fails there.
+        auto walk = [&](auto checked, int b, int f) {
+            auto valid = [&](int j0) { return decltype(checked)::value ? lane < f - j0 : true; };
             float c0, s0, c1, s1, c2, s2;
             dir(b, c0, s0);
             dir(b + 64, c1, s1);
             for (int j0 = b; j0 < f; j0 += 192) {
                 dir(j0 + 128, c2, s2);
-                vote(lane < f - j0, c0, s0);
+                vote(valid(j0), c0, s0);
                 if (j0 + 64 >= f) break;   // uniform
                 dir(j0 + 192, c0, s0);
-                vote(lane < f - j0 - 64, c1, s1);
+                vote(valid(j0 + 64), c1, s1);
                 if (j0 + 128 >= f) break;   // uniform
                 dir(j0 + 256, c1, s1);
-                vote(lane < f - j0 - 128, c2, s2);
+                vote(valid(j0 + 128), c2, s2);
             }
         };
-        while (mask) {
-            const int k = __builtin_ctzll(mask);
-            const int e = k + __builtin_ctzll(~(mask >> k));   // bit 63 is never set
-            mask &= ~(((1ull << (e - k)) - 1ull) << k);
-            const int jb = js + (k * L) / 63, je = js + (e * L) / 63;   // js < J, je <= js + J
-            if (jb < J) walk(jb, je < J ? je : J);
-            if (je > J) walk(jb > J ? jb - J : 0, je - J);
-        }
+        auto runs = [&](auto checked) {
+            while (mask) {
+                const int k = __builtin_ctzll(mask);
+                const int e = k + __builtin_ctzll(~(mask >> k));   // bit 63 is never set
+                mask &= ~(((1ull << (e - k)) - 1ull) << k);
+                const int jb = js + (k * L) / 63, je = js + (e * L) / 63;   // js < J, je <= js + J
+                if (jb < J) walk(checked, jb, je < J ? je : J);
+                if (je > J) walk(checked, jb > J ? jb - J : 0, je - J);
+            }
+        };
+        // intervals of floor(L / 63) >= 64 samples (uniform)
+        if (!kLdsDirs && L >= 64 * 63 && (L == J || L + 64 <= J)) runs(BoolTag<false>{});
+        else runs(BoolTag<true>{});
     }
 }
 
@@ -1278,11 +1319,13 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
     // cells of one column over the LDS banks)
     const int lrw = half ? 30 - __clz(G) : 31 - __clz(G);   // log2 of the words of a row
     const int padded = words + bw;
-    // LDS: the sample directions (when they fit), then the band tile
+    // LDS: the sample directions (when they fit), then the band tile (16-bit
+    // counters: after one more word, which takes cell -1 of the first row)
     const bool lds_dirs = I.sdir_lds != 0;
     float* ldir = reinterpret_cast<float*>(sm);
-    uint32_t* tile = sm + (lds_dirs ? 2 * J : 0);
-    for (int e = threadIdx.x; e < padded; e += blockDim.x) tile[e] = 0u;
+    const int pre = half ? 1 : 0;
+    uint32_t* tile = sm + (lds_dirs ? 2 * J : 0) + pre;
+    for (int e = threadIdx.x; e < padded + pre; e += blockDim.x) tile[e - pre] = 0u;
     if (lds_dirs)
         for (int e = threadIdx.x; e < J; e += blockDim.x) {
             ldir[e] = I.scs[e];
@@ -1294,12 +1337,24 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
         else sample_band_walk<true, false>(I, wi, recs, ldir, tile, r0, r1);
     } else {
         if (half) sample_band_walk<false, true>(I, wi, recs, ldir, tile, r0, r1);
-        else sample_band_walk<false, false>(I, wi, recs, ldir, tile, r0, r1);
+        else sample_band_walk<false, false>(I, wi, recs, ldir, sm, r0, r1);   // tile == sm: its base folds away
     }
     __syncthreads();
     const int chunk = wi.z / I.schunk;
     uint32_t* dst = part + I.spart_off + ((int64_t)chunk * I.snb + band) * words;
-    for (int e = threadIdx.x; e < words; e += blockDim.x) dst[e] = tile[e + (e >> lrw)];
+    if (half) {
+        // cells -1 and G of a row (see the band walk) join cells 0 and G - 1
+        const int last = (1 << lrw) - 1;
+        for (int e = threadIdx.x; e < words; e += blockDim.x) {
+            const int m = e & last, pe = e + (e >> lrw);
+            uint32_t v = tile[pe];
+            if (m == 0) v += tile[pe - 1] >> 16;
+            if (m == last) v += tile[pe + 1] << 16;
+            dst[e] = v;
+        }
+    } else {
+        for (int e = threadIdx.x; e < words; e += blockDim.x) dst[e] = tile[e + (e >> lrw)];
+    }
 }
 
 // grid cell = sum over the instance's circle chunks of its band slot.  With
@@ -1970,7 +2025,7 @@ SampleLayout sample_plan(int G, int J, int64_t n) {
             L.bw = (int)(cells / G);
             L.chunk = ch;
             L.part_words = nch * (GG / 2);
-            const size_t tile = (size_t)cells * 2 + (size_t)(cells / G) * 4;   // + one pad word per row
+            const size_t tile = (size_t)cells * 2 + (size_t)(cells / G) * 4 + 4;   // + one pad word per row, one before
             L.dirs_lds = tile + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
             L.lds_bytes = tile + (L.dirs_lds ? (size_t)J * 8 : 0);
             return L;

@@ -53,9 +53,10 @@ struct HostBuf {
     T* as() const { return static_cast<T*>(ptr); }
 };
 
-// Angle tables of B bins (5 B floats: boundary cos, sin; centre angle, cos,
-// sin) and the in-disk cross ranges of a G x G grid (2 G int16), written into
-// host memory.
+// Angle tables of B bins (angle_table_floats(B) floats: boundary cos and sin,
+// each followed by kDirPad NaNs; centre angle, cos, sin) and the in-disk cross
+// ranges of a G x G grid (2 G int16), written into host memory.
+size_t angle_table_floats(int B);
 void fill_angle_tables(float* h, int B);
 void fill_disk_table(int16_t* h, int G);
 
