@@ -1224,15 +1224,19 @@ __device__ __forceinline__ void sample_band_walk(const Inst& I, const int4 wi, c
             const float rinv = recip_1_4(1.0f - s2);
             const float u = s0 * rinv, v = s1 * rinv;
             const int ixf = floor_to_int(__builtin_fmaf(u, hg, hg));
-            const int iy = clamp_int(floor_to_int(__builtin_fmaf(v, hg, hg)), G - 1);
+            const int iyf = floor_to_int(__builtin_fmaf(v, hg, hg));
+            // 16-bit tiles: rows -1 and G have tile rows of their own in the
+            // first and the last band (folded into rows 0 and G - 1 when the
+            // tile is stored, like the columns below)
+            const int iy = kHalf ? iyf : clamp_int(iyf, G - 1);
             const int ry = iy - r0;
             const bool ok = valid && s2 <= 0.0f && (unsigned)ry < rows;
             // tile rows of tw words: G/2 (+1 pad) with 16-bit counters, cells
             // 2m and 2m + 1 of a row in word m; G (+1) with 32-bit ones
             if (kHalf) {
-                // The column is not clamped here.  A voted sample has s_z <= 0,
+                // Neither coordinate is clamped here.  A voted sample has s_z <= 0,
                 // and the frame and the directions are unit vectors to a few
-                // ulps, so |u| <= 1 + 2^-16 and ixf lies in [-1, G] (G <= 4096).
+                // ulps, so |u|, |v| <= 1 + 2^-16 and ixf, iyf lie in [-1, G] (G <= 4096).
                 // Cell G of row r lands in the low half of the row's pad word,
                 // cell -1 in the high half of the word before the row (the pad
                 // of row r - 1, or a word before the tile); the tile store adds
@@ -1311,14 +1315,17 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
     const Inst& I = insts[wi.x];
     const int G = I.G, J = I.J, bw = I.sbw;
     const int band = wi.y;
-    const int r0 = band * bw, r1 = r0 + bw;
     const int cells = bw * G;
     const bool half = I.shalf != 0;   // 16-bit counters: cells 2m and 2m + 1 share word m
     const int words = half ? cells >> 1 : cells;
+    // 16-bit tiles of the first and the last band take row -1, resp. row G,
+    // in a tile row of their own: the walk counts rows [r0, r1)
+    const bool top = half && band == 0, bottom = half && band == I.snb - 1;
+    const int r0 = band * bw - (top ? 1 : 0), r1 = (band + 1) * bw + (bottom ? 1 : 0);
     // the tile's rows carry one pad word each (an odd stride spreads the
     // cells of one column over the LDS banks)
     const int lrw = half ? 30 - __clz(G) : 31 - __clz(G);   // log2 of the words of a row
-    const int padded = words + bw;
+    const int padded = (r1 - r0) * ((1 << lrw) + 1);
     // LDS: the sample directions (when they fit), then the band tile (16-bit
     // counters: after one more word, which takes cell -1 of the first row)
     const bool lds_dirs = I.sdir_lds != 0;
@@ -1343,13 +1350,22 @@ __global__ __launch_bounds__(1024) void k_sample_vote(const Inst* __restrict__ i
     const int chunk = wi.z / I.schunk;
     uint32_t* dst = part + I.spart_off + ((int64_t)chunk * I.snb + band) * words;
     if (half) {
-        // cells -1 and G of a row (see the band walk) join cells 0 and G - 1
-        const int last = (1 << lrw) - 1;
-        for (int e = threadIdx.x; e < words; e += blockDim.x) {
-            const int m = e & last, pe = e + (e >> lrw);
+        // cells -1 and G of a row (see the band walk) join cells 0 and G - 1,
+        // rows -1 and G join rows 0 and G - 1
+        const int last = (1 << lrw) - 1, tw = last + 2;
+        auto word = [&](int t, int m) {   // tile row t, word m, with its row's outer cells
+            const int pe = t * tw + m;
             uint32_t v = tile[pe];
             if (m == 0) v += tile[pe - 1] >> 16;
             if (m == last) v += tile[pe + 1] << 16;
+            return v;
+        };
+        const int t0 = top ? 1 : 0;
+        for (int e = threadIdx.x; e < words; e += blockDim.x) {
+            const int m = e & last, r = e >> lrw;
+            uint32_t v = word(r + t0, m);
+            if (top && r == 0) v += word(0, m);
+            if (bottom && r == bw - 1) v += word(r + t0 + 1, m);
             dst[e] = v;
         }
     } else {
@@ -2025,7 +2041,9 @@ SampleLayout sample_plan(int G, int J, int64_t n) {
             L.bw = (int)(cells / G);
             L.chunk = ch;
             L.part_words = nch * (GG / 2);
-            const size_t tile = (size_t)cells * 2 + (size_t)(cells / G) * 4 + 4;   // + one pad word per row, one before
+            // rows of G/2 + 1 words (one pad), two more rows (rows -1 and G
+            // in the first and the last band), one word before
+            const size_t tile = ((size_t)(cells / G) + 2) * ((size_t)G * 2 + 4) + 4;
             L.dirs_lds = tile + (size_t)J * 8 <= 160 * 1024 ? 1 : 0;
             L.lds_bytes = tile + (L.dirs_lds ? (size_t)J * 8 : 0);
             return L;

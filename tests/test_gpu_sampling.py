@@ -66,6 +66,8 @@ def assert_ls(orc, r, P, Q, mask):
     (4096, 65536, 40, 8),     # the largest grid and sample count
     (2048, 37, 300, 9),       # whole-circle walks with a row margin above 4095
     (4096, 20, 200, 10),
+    (1024, 8192, 600, 11),    # the benchmark's G and J: directions from global memory, runs without an end test
+    (256, 8200, 400, 12),     # J not a multiple of 64 there: the last step reads the tables' NaN pads
 ])
 def test_sample_grid_bit_exact(aor, orc, G, J, n, seed):
     inst = synth.make_instance(n, 5100 + seed)
@@ -94,7 +96,9 @@ def test_sample_grid_special_inputs(aor, orc):
     D[:, 10] = (1, 1, 1)
     D[:, 11] = (-1, 1, 1)
     Z = np.zeros_like(D)
-    for G, J in ((64, 512), (128, 1000)):
+    # the equator's samples reach u = 1 exactly (a cell one past the grid
+    # before the clamp); the last two also walk runs without an end test
+    for G, J in ((64, 512), (128, 1000), (1024, 8192), (256, 8200)):
         g, _ = gpu_sample_grid(aor, Z, D, G, J)
         assert np.array_equal(g, orc.sample_grid(Z, D, G, J))
 
