@@ -117,6 +117,7 @@ struct CoarseEmit {
     int db = 0;            // second cell of a clean line relative to its first: 1 - 2 off
     int sh = 0;            // cell k of a row handle at handle[k + sh]: 1 - off
     uint32_t d_up = 0, d_dn = 0, e_up = 0, e_dn = 0;   // pair2's increments by each line's step
+    int du = 0, dd = 0;    // pair2's cell moves (1 - off up, -off down)
     __device__ __forceinline__ uint32_t* row_of(int j) const { return tile + ((int)__umul24(j >> 1, sw) + jofs); }
     __device__ __forceinline__ static uint32_t inc_of(int j) { return 1u << ((j & 1) << 4); }
     __device__ __forceinline__ void operator()(int j, int klo, int khi) {
@@ -135,8 +136,14 @@ struct CoarseEmit {
         d_dn = off ? 0x10001u : 0x10000u;
         e_up = off ? 0u : 0x10000u;
         e_dn = off ? 0x10000u : 0u;
+        du = 1 - off;
+        dd = -off;
         return row_of(j) + (off - 1);
     }
+    // a cell handle (the word of cell r of a row handle) and its index
+    __device__ __forceinline__ static uint32_t* cell_of(uint32_t* row, int r) { return row + r; }
+    __device__ __forceinline__ static int index_of(uint32_t* row, uint32_t* cell) { return (int)(cell - row); }
+    __device__ __forceinline__ uint32_t* next_cell(uint32_t* cell) const { return cell + sw; }
     __device__ __forceinline__ uint32_t* next_row(uint32_t* row) const { return row + sw; }
     __device__ __forceinline__ uint32_t* rows_after(uint32_t* row, int n) const { return row + n * sw; }
     // a general range of the line with parity H
@@ -157,12 +164,16 @@ struct CoarseEmit {
         atomicAdd(row + r, inc);
         atomicAdd(row + r + db, second ? inc : 0u);
     }
-    // both lines of the row from rows r0 -> r1 -> r2: the line 2m + 1 cell
-    // r1 - 1 + off shares its word with line 2m's second cell, if any
-    __device__ __forceinline__ void pair2(uint32_t* row, int r0, int r1, int r2, bool up0, bool up1) const {
-        atomicAdd(row + r0, 1u);
-        atomicAdd(row + r1, up0 ? d_up : d_dn);
-        atomicAdd(row + r2, up1 ? e_up : e_dn);
+    // both lines of the row from the cell handle of r0 -> r1 -> r2 (r1 = r0 +
+    // (up0 ? 1 : 0) - off, r2 likewise): the line 2m + 1 cell r1 - 1 + off
+    // shares its word with line 2m's second cell, if any; returns r2's handle
+    __device__ __forceinline__ uint32_t* pair2(uint32_t* c0, bool up0, bool up1) const {
+        uint32_t* c1 = c0 + (up0 ? du : dd);
+        uint32_t* c2 = c1 + (up1 ? du : dd);
+        atomicAdd(c0, 1u);
+        atomicAdd(c1, up0 ? d_up : d_dn);
+        atomicAdd(c2, up1 ? e_up : e_dn);
+        return c2;
     }
 };
 

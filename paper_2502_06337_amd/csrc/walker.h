@@ -414,12 +414,17 @@ AOR_HD __forceinline__ void walk_search(float aL, float bL, float c, int sel, fl
 // 2m + 1 in one row m instead: row_start(j, off) returns the row of line j,
 // next_row(row) the following one, rows_after(row, n) the n-th following
 // one, range_h<H>(row, klo, khi) emits a general range of the line with
-// parity H in that row, pair_h<H>(row, r, second) its clean-state cells, and
-// pair2(row, r0, r1, r2, up0, up1) those of both lines of a row walked
-// clean from row r0 (line 2m: cell r0 - 1 + off, and r1 - 1 + off if it
-// differs; line 2m + 1: cell r1 - 1 + off, and r2 - 1 + off if it differs).  An emitter with kAudit set also receives, on every clean
-// line, the values at the two rows next to the evaluated one (audit(fb, fa)),
-// so that a host test can check what the certificates claim.  kLattice: every vertex coordinate y0 + k*hy is exact and
+// parity H in that row, pair_h<H>(row, r, second) its clean-state cells;
+// cell_of(row, r) is a handle of cross index r in a row, index_of(row, cell)
+// gives r back, next_cell(cell) is the same index in the following row, and
+// pair2(cell, up0, up1) emits the cells of both lines of a row walked clean
+// from row r0 = the cell's index (r1 = r0 + up0 - off, r2 = r1 + up1 - off;
+// line 2m: cell r0 - 1 + off, and r1 - 1 + off if it differs; line 2m + 1:
+// cell r1 - 1 + off, and r2 - 1 + off if it differs) and returns r2's handle.
+// An emitter with kAudit set also receives, on every clean line, the values
+// at the two rows next to the evaluated one (audit(fb, fa)), so that a host
+// test can check what the certificates claim.  kLattice: every vertex
+// coordinate y0 + k*hy is exact and
 // so are sums of them (the coarse grid), so the evaluated row's coordinate is
 // carried from line to line instead of recomputed.
 template <bool kLattice = false, class Emit>
@@ -591,38 +596,45 @@ AOR_HD __forceinline__ void walk_certified(float aL, float bL, float c, int sel,
         }
         const auto row_end = emit.rows_after(row, (ce - j) >> 1);
         const bool last_alone = ((ce - j) & 1) != 0;
-        for (; row != row_end; row = emit.next_row(row)) {
+        // fast pairs carry a handle of cell r of the row (r itself is taken
+        // back from it where the exact step needs it)
+        auto cell = emit.cell_of(row, r);
+        for (; row != row_end; row = emit.next_row(row), cell = emit.next_cell(cell)) {
             const float xa = x + hx, xb = xa + hx;
             const float f0 = vertex_F_fast(sc, tsa, tsb, nsc, xa, yr);
             const bool up0 = f0 > 0.0f;
             const float y1 = yr + (up0 ? dy_up : dy_dn);
             const float f1 = vertex_F_fast(sc, tsa, tsb, nsc, xb, y1);
-            if (fabsf(lastf) > T && fabsf(f0) > T && fabsf(f1) > T) {
+            // one three-way minimum of magnitudes and one compare (the values
+            // are finite: risky curves never reach the walk)
+            if (fminf(fminf(fabsf(lastf), fabsf(f0)), fabsf(f1)) > T) {
                 const bool up1 = f1 > 0.0f;
-                const int r1 = r + (up0 ? 1 : 0) - off;
-                const int r2 = r1 + (up1 ? 1 : 0) - off;
                 if constexpr (Emit::kAudit) {
                     // test builds only: the rule's values agree in sign with the
                     // fast ones, and the certificates hold on both lines
+                    const int rc = emit.index_of(row, cell);
+                    const int r1 = rc + (up0 ? 1 : 0) - off;
                     const float xxa = xa * xa, axa = sa * xa, xxb = xb * xb, axb = sa * xb;
                     const float ea = vertex_F(sb, sc, xxa, axa, yr), eb = vertex_F(sb, sc, xxb, axb, y1);
                     emit.audit(up0 ? ea : -ea, -1.0f);
                     emit.audit(up1 ? eb : -eb, -1.0f);
-                    emit.audit(vertex_F(sb, sc, xxa, axa, y0 + (float)(r - 1) * hy),
-                               vertex_F(sb, sc, xxa, axa, y0 + (float)(r + 1) * hy));
+                    emit.audit(vertex_F(sb, sc, xxa, axa, y0 + (float)(rc - 1) * hy),
+                               vertex_F(sb, sc, xxa, axa, y0 + (float)(rc + 1) * hy));
                     emit.audit(vertex_F(sb, sc, xxb, axb, y0 + (float)(r1 - 1) * hy),
                                vertex_F(sb, sc, xxb, axb, y0 + (float)(r1 + 1) * hy));
                 }
-                emit.pair2(row, r, r1, r2, up0, up1);
-                r = r2;
+                cell = emit.pair2(cell, up0, up1);   // now at r2
                 yr = y1 + (up1 ? dy_up : dy_dn);
                 x = xb;
                 // the state stays clean: lastf keeps a value beyond T
             } else {
+                r = emit.index_of(row, cell);
                 step(fabsf(lastf) > T, range0, pair0);
                 step(fabsf(lastf) > T, range1, pair1);
+                cell = emit.cell_of(row, r);
             }
         }
+        r = emit.index_of(row, cell);
         if (last_alone) step(fabsf(lastf) > T, range0, pair0);
     } else {
         auto cur = emit.start(cs, off);

@@ -84,11 +84,20 @@ struct CoarseHostEmit {
         clean_cell(row + H, r - 1 + offs);
         if (second) clean_cell(row + H, r - offs);
     }
-    void pair2(int row, int r0, int r1, int r2, bool up0, bool up1) {
-        clean_cell(row, r0 - 1 + offs);
-        if (up0 != (offs != 0)) clean_cell(row, r1 - 1 + offs);
-        clean_cell(row + 1, r1 - 1 + offs);
-        if (up1 != (offs != 0)) clean_cell(row + 1, r2 - 1 + offs);
+    // a cell handle: row and cross index
+    struct Cell {
+        int row, r;
+    };
+    static Cell cell_of(int row, int r) { return {row, r}; }
+    static int index_of(int row, Cell c) { return c.r; }
+    static Cell next_cell(Cell c) { return {c.row + 2, c.r}; }
+    Cell pair2(Cell c, bool up0, bool up1) {
+        const int r0 = c.r, r1 = r0 + (up0 ? 1 : 0) - offs, r2 = r1 + (up1 ? 1 : 0) - offs;
+        clean_cell(c.row, r0 - 1 + offs);
+        if (up0 != (offs != 0)) clean_cell(c.row, r1 - 1 + offs);
+        clean_cell(c.row + 1, r1 - 1 + offs);
+        if (up1 != (offs != 0)) clean_cell(c.row + 1, r2 - 1 + offs);
+        return {c.row, r2};
     }
     void audit(float below, float above) {
         counts->steps++;
