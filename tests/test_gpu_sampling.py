@@ -68,6 +68,8 @@ def assert_ls(orc, r, P, Q, mask):
     (4096, 20, 200, 10),
     (1024, 8192, 600, 11),    # the benchmark's G and J: directions from global memory, runs without an end test
     (256, 8200, 400, 12),     # J not a multiple of 64 there: the last step reads the tables' NaN pads
+    (1024, 8046, 400, 13),    # window of 4032 samples: checkpoint intervals of exactly 64, no end test
+    (1024, 8044, 400, 14),    # window of 4031: intervals of 63, runs with the end test
 ])
 def test_sample_grid_bit_exact(aor, orc, G, J, n, seed):
     inst = synth.make_instance(n, 5100 + seed)
