@@ -1,7 +1,7 @@
 """The allocation-free entry point (est_rotation_noalloc_dev) through the C
 ABI: bit-identical to est_rotation_dev (result, least-squares rotation and
 mask) on two calls in a row, the second smaller than the first, with and
-without refinement; a solve that does not fit its static scratch array is
+without refinement and with the sampling rule; a solve that does not fit its static scratch array is
 refused with ENOMEM before anything runs."""
 import ctypes as C
 
@@ -54,6 +54,24 @@ def test_noalloc_equals_est_rotation_dev(lib, M):
         P = torch.from_numpy(inst.P).cuda()
         Q = torch.from_numpy(inst.Q).cuda()
         prm = SolveParams(refine_grid=M, angle_bins=3600 if M else 360)
+        got = solve(lib, "est_rotation_noalloc_dev", P, Q, prm)
+        ref = solve(lib, "est_rotation_dev", P, Q, prm)
+        assert got[0] == 0
+        assert_same(got, ref)
+
+
+@pytest.mark.parametrize("G,J", [(256, 2048), (1024, 8192)])
+def test_noalloc_sampling_rule(lib, G, J):
+    """The literal sampling rule through the allocation-free entry point: its
+    circle records, partial tiles and padded direction tables (staged in the
+    static array's table area) give the same bits as est_rotation_dev, on two
+    calls in a row, the second smaller."""
+    from paper_2502_06337_amd import SolveParams
+    for n, seed in ((20000, 63), (5000, 64)):
+        inst = synth.make_instance(n, seed, outlier_rate=0.9)
+        P = torch.from_numpy(inst.P).cuda()
+        Q = torch.from_numpy(inst.Q).cuda()
+        prm = SolveParams(grid=G, angle_bins=360, vote_rule=1, circle_samples=J)
         got = solve(lib, "est_rotation_noalloc_dev", P, Q, prm)
         ref = solve(lib, "est_rotation_dev", P, Q, prm)
         assert got[0] == 0
