@@ -442,8 +442,8 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the path shards by instances or coarse-grid bands across GPUs, which is not built here)",
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(sharding by instances or coarse-grid bands across GPUs is a design, not code)",
               file=sys.stderr)
         return 2
 
